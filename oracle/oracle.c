@@ -324,8 +324,10 @@ int64_t orc_bin(const orc_params *P, int64_t N, const double *r, const double *z
     int64_t nk = b1 - b0;
     double r_lo, r_hi;
     if (nk > 0) {
-      r_lo = (zr == 0) ? kr[b0].key : 0.5 * (kr[b0 - 1].key + kr[b0].key);
-      r_hi = (zr == nr - 1) ? kr[b1 - 1].key : 0.5 * (kr[b1 - 1].key + kr[b1].key);
+      /* edges half-way to the neighbouring ranks; the grid ends at the
+       * first and last active particle */
+      r_lo = (b0 == 0) ? kr[b0].key : 0.5 * (kr[b0 - 1].key + kr[b0].key);
+      r_hi = (b1 == na) ? kr[b1 - 1].key : 0.5 * (kr[b1 - 1].key + kr[b1].key);
     } else {
       r_lo = r_hi = 0.0;
     }
@@ -338,8 +340,10 @@ int64_t orc_bin(const orc_params *P, int64_t N, const double *r, const double *z
       cell_start[c] = (int32_t)s0;
       double z_lo = 0.0, z_hi = 0.0;
       if (s1 > s0) {
-        z_lo = (l == 0) ? 0.0 : 0.5 * (kz[s0 - 1].key + kz[s0].key);
-        z_hi = (l == nz - 1) ? kz[s1 - 1].key : 0.5 * (kz[s1 - 1].key + kz[s1].key);
+        /* the lowest occupied cell of a zone starts at the midplane, the
+         * highest ends at its topmost particle */
+        z_lo = (s0 == b0) ? 0.0 : 0.5 * (kz[s0 - 1].key + kz[s0].key);
+        z_hi = (s1 == b1) ? kz[s1 - 1].key : 0.5 * (kz[s1 - 1].key + kz[s1].key);
       }
       double V;
       double r_c = P->column ? P->r_col : 0.5 * (r_lo + r_hi);
@@ -410,6 +414,16 @@ int64_t orc_collide_cell(const orc_params *P, const double prim[ORC_GAS_FIELDS],
     for (int32_t j = 0; j < n; ++j) {
       row[j] = orc_rate(P, &g, &pp[i], &pp[j]);
       Ri += row[j];
+    }
+    if (!(Ri > 0.0)) {
+      /* row i has no partner left (its stored sum was rounding residue):
+       * clear it and count a null event */
+      rr[i] = 0.0;
+      if (evlog && e < log_cap) {
+        evlog[e].i = i; evlog[e].j = -1; evlog[e].outcome = -1; evlog[e].pad = 0;
+      }
+      ++e;
+      continue;
     }
     int32_t j = orc_select(row, n, u3 * Ri);
     double dv = (P->kernel == ORC_K_PHYSICAL) ? orc_rel_velocity(P, &g, &pp[i], &pp[j]) : 0.0;
