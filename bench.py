@@ -1,0 +1,261 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched collision step on one MI355X.
+
+Workload: the batched collision step -- 4096 independent cells with
+log-uniform particle counts in [64, 1024] (1.40e6 particles), log-uniform
+masses 1e-12..1e2 g, random local gas, exactly 1000 collisions per cell per
+step (seeded, synthetic).  A step is one mcd_step: every cell builds its rate
+matrix row sums and performs its 1000 events (selection, outcome, rate
+update); particles stay resident in HBM.
+
+Reports collisions/s and algorithmic rate-pair evaluations/s for the four
+forms {FP64, mixed} x {plain, batched}; the headline `value` is the mixed
+batched form.  Adds the roofline of the collision kernel (vector-ALU bound),
+the FP64 CPU oracle timed on a bounded sample of the same workload, and the
+errors of the GPU forms against the oracle.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "collisions/sec + rate-pair evals/sec, mixed vs FP64 plain, at stated error"
+# floating-point operations of one pair evaluation of the physical kernel,
+# counted from the oracle's pair functions with per-particle and per-cell
+# quantities precomputed (+ - * / sqrt = 1): Brownian 3, turbulence
+# (intermediate regime) 14, drift and settling 9, sqrt 1, cross-section and
+# kernel 4, two directed swarm rates with grouping 2 x 4
+F_PAIR = 39
+PEAK_FP32_TFLOPS = 157.3
+EVENTS_PER_CELL = 1000
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def pair_evals(counts, events):
+    counts = counts.astype("float64")
+    return float((counts * (counts + 1) / 2).sum() + events * counts.sum())
+
+
+def run_mode(work, precision, schedule, steps, warmup):
+    import torch
+    from paper_2507_21239_amd import api
+    dev = api.to_device(work["particles"])
+    sim = api.Simulation(work["params"], dev, precision=precision, schedule=schedule)
+    sim.bin(api.cells_to_device(work["cells"]))
+    for _ in range(warmup):
+        sim.step(0.0, EVENTS_PER_CELL, 1)
+    torch.cuda.synchronize()
+    ev0 = sim.stats()["events"]
+    stream = torch.cuda.current_stream()
+    marks = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in marks:
+        a.record(stream)
+        sim.step(0.0, EVENTS_PER_CELL, 1)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = sim.stats()
+    sim.close()
+    kernel_ms = sum(a.elapsed_time(b) for a, b in marks) / steps
+    return dict(wall_s=wall, ms_per_step=wall / steps * 1e3, kernel_ms=kernel_ms,
+                events=st["events"] - ev0)
+
+
+def error_report(work, n_sample=8):
+    """Errors of the GPU forms against the FP64 oracle on sampled cells."""
+    import ctypes as C
+
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_2507_21239_amd import api
+    from paper_2507_21239_amd import workloads as W
+
+    cs = work["cells"]["cell_start"]
+    sizes = np.diff(cs)
+    rng = np.random.default_rng(123)
+    pick = sorted(set([int(np.argmax(sizes))] + list(rng.choice(len(sizes), n_sample - 1, replace=False))))
+    out = {"sample_cells": len(pick)}
+    # rate matrices
+    worst = {}
+    for precision in ("fp64", "mixed"):
+        dev = api.to_device(work["particles"])
+        sim = api.Simulation(work["params"], dev, precision=precision)
+        sim.bin(api.cells_to_device(work["cells"]))
+        w = 0.0
+        for c in pick:
+            n = int(sizes[c])
+            Rg, _ = sim.rates(c, n)
+            Ro, _ = O.cell_rates(work["params"], work["cells"]["gas"][c],
+                                 work["cells"]["order"][cs[c]:cs[c + 1]],
+                                 work["particles"]["m"], work["particles"]["M"])
+            w = max(w, float(np.max(np.abs(Rg.cpu().numpy() - Ro) / Ro)))
+        worst[precision] = w
+        sim.close()
+    out["rate_max_rel_err_fp64"] = worst["fp64"]
+    out["rate_max_rel_err_mixed"] = worst["mixed"]
+    # one step: FP64 event sequences and final masses of sampled cells
+    logs = {}
+    masses = {}
+    for precision in ("fp64", "mixed"):
+        dev = api.to_device(work["particles"])
+        sim = api.Simulation(work["params"], dev, precision=precision)
+        sim.bin(api.cells_to_device(work["cells"]))
+        buf = torch.full((len(sizes) * EVENTS_PER_CELL * 4,), -7, dtype=torch.int32, device="cuda")
+        sim.set_event_log(buf, EVENTS_PER_CELL)
+        sim.step(0.0, EVENTS_PER_CELL, 1)
+        logs[precision] = buf.cpu().numpy().reshape(len(sizes), EVENTS_PER_CELL, 4)
+        masses[precision] = dev["m"].cpu().numpy()
+        sim.close()
+    mism, mrel = 0, 0.0
+    om_all, gm_all = [], []
+    for c in pick:
+        sub = W.subset_cells(work, np.array([c]))
+        part = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in sub["particles"].items()}
+        lg = np.zeros(EVENTS_PER_CELL, dtype=O.EVENT_DTYPE)
+        st = np.zeros(1, dtype=O.STATS_DTYPE)
+        O.lib().orc_collide_cell(C.byref(O.make_params(sub["params"])),
+                                 O._ptr(np.ascontiguousarray(sub["cells"]["gas"][0]), C.c_double),
+                                 c, 0, int(sizes[c]),
+                                 O._ptr(np.ascontiguousarray(sub["cells"]["order"]), C.c_int32),
+                                 O._ptr(part["m"], C.c_double), O._ptr(part["M"], C.c_double),
+                                 None, len(part["m"]), 0.0, EVENTS_PER_CELL, lg.ctypes.data,
+                                 EVENTS_PER_CELL, st.ctypes.data)
+        o = np.stack([lg["i"], lg["j"], lg["outcome"]], axis=1)
+        mism += int(np.any(o != logs["fp64"][c, :, :3], axis=1).sum())
+        g = masses["fp64"][cs[c]:cs[c + 1]]
+        mrel = max(mrel, float(np.max(np.abs(g - part["m"]) / part["m"])))
+        om_all.append(np.log10(part["m"]))
+        gm_all.append(np.log10(masses["mixed"][cs[c]:cs[c + 1]]))
+    out["fp64_event_mismatches"] = mism
+    out["fp64_events_compared"] = len(pick) * EVENTS_PER_CELL
+    out["fp64_mass_max_rel_err"] = mrel
+    from scipy import stats as sst
+    ks = sst.ks_2samp(np.concatenate(om_all), np.concatenate(gm_all))
+    out["mixed_vs_oracle_logm_ks_D"] = float(ks.statistic)
+    out["mixed_vs_oracle_logm_ks_p"] = float(ks.pvalue)
+    return out
+
+
+def cpu_baseline(work, target_s=12.0):
+    """The FP64 oracle on a bounded sample of cells of the same workload,
+    threads over cells on every host core."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2507_21239_amd import workloads as W
+
+    threads = os.cpu_count() or 1
+    rng = np.random.default_rng(7)
+    n_cells = len(work["cells"]["cell_start"]) - 1
+    k = max(threads, 8)
+    used = 0.0
+    evs = 0
+    ncells = 0
+    perm = rng.permutation(n_cells)
+    while used < target_s and ncells < n_cells:
+        cells = np.sort(perm[ncells:ncells + k])
+        sub = W.subset_cells(work, cells)
+        part = {kk: (v.copy() if isinstance(v, np.ndarray) else v) for kk, v in sub["particles"].items()}
+        t0 = time.perf_counter()
+        out = O.collide_all(sub["params"], sub["cells"], 0, part, 0.0, EVENTS_PER_CELL, threads=threads)
+        used += time.perf_counter() - t0
+        evs += int(out["stats"]["events"].sum())
+        ncells += len(cells)
+        k = min(2 * k, n_cells - ncells) if used < target_s / 4 else k
+    return dict(value=evs / used, unit="collisions/s", cores=threads, kind="oracle",
+                sample=f"{ncells} of {n_cells} cells of the same workload, {EVENTS_PER_CELL} events "
+                       f"each ({evs} events), FP64, {used:.1f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-error", action="store_true", help="skip the error report")
+    ap.add_argument("--modes", default="all", help="all | headline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the collision step has no multi-GPU path in this "
+              "build (cells would shard by radial zones; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2507_21239_amd import workloads as W
+
+    assert torch.cuda.is_available(), "no GPU"
+    work = W.c4_batched(seed=0, events=EVENTS_PER_CELL)
+    counts = np.diff(work["cells"]["cell_start"])
+    evals = pair_evals(counts, EVENTS_PER_CELL)
+    log("workload", len(counts), "cells", int(counts.sum()), "particles", f"{evals:.3e} pair evals/step")
+
+    modes = [("mixed", "batched")] if args.modes == "headline" else \
+        [("fp64", "plain"), ("fp64", "batched"), ("mixed", "plain"), ("mixed", "batched")]
+    res = {}
+    for precision, schedule in modes:
+        log("timing", precision, schedule)
+        r = run_mode(work, precision, schedule, args.steps, args.warmup)
+        r["collisions_per_s"] = r["events"] / r["wall_s"]
+        r["pair_evals_per_s"] = evals * args.steps / r["wall_s"]
+        res[f"{precision}_{schedule}"] = r
+        log(precision, schedule, f"{r['ms_per_step']:.3f} ms/step", f"{r['collisions_per_s']:.3e} coll/s")
+    head = res["mixed_batched"]
+    achieved = F_PAIR * evals / (head["kernel_ms"] * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": head["collisions_per_s"],
+        "unit": "collisions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "precision": "FP32 pair rates; FP64 masses, prefix sums, row-sum state and time",
+        "data": "synthetic",
+        "config": {"workload": "batched collision step: 4096 cells, counts log-uniform [64,1024], "
+                               "masses log-uniform 1e-12..1e2 g, random gas, 1000 events/cell",
+                   "cells": int(len(counts)), "particles": int(counts.sum()),
+                   "events_per_cell": EVENTS_PER_CELL, "schedule": "batched"},
+        "pair_evals_per_s": head["pair_evals_per_s"],
+        "forms": {k: {"collisions_per_s": v["collisions_per_s"], "pair_evals_per_s": v["pair_evals_per_s"],
+                      "ms_per_step": v["ms_per_step"], "kernel_ms": v["kernel_ms"]} for k, v in res.items()},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "collide_batched<float>", "flops_per_pair": F_PAIR,
+                     "pair_evals_per_launch": evals},
+    }
+    if "fp64_plain" in res:
+        out["speedup_mixed_batched_vs_fp64_plain"] = head["collisions_per_s"] / res["fp64_plain"]["collisions_per_s"]
+    if not args.no_error:
+        log("error report")
+        out["error"] = error_report(work)
+    if not args.no_cpu:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(work)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * mcd.h -- C ABI of the MI355X (gfx950) library for the representative-particle
+ * collision step of mcdust (arXiv 2507.21239).
+ *
+ * The paper (Summary) states the problem this library solves: a static,
+ * vertically isothermal power-law gas disk holds N representative particles
+ * (Zsom & Dullemond 2008), each standing for a swarm of identical bodies;
+ * particles are binned into an adaptive grid whose cells hold equal numbers
+ * of representative particles; inside each cell particles collide with the
+ * outcomes sticking, fragmentation and erosion; particles are transported
+ * radially and vertically.  The Benchmark section's table fixes the disk:
+ * Sigma_g(1 AU) = 1000 g/cm^2, T(1 AU) = 280 K, alpha = 1e-3, v_frag = 10 m/s,
+ * erosion mass ratio 10, p = 1, q = 0.5.
+ *
+ * Conventions
+ *  - CGS units.  All particle arrays are DEVICE pointers owned by the caller
+ *    (allocate them with hipMalloc or as torch tensors); the library keeps
+ *    non-owning views and never frees them.  They must outlive the context.
+ *  - All device work is enqueued on the caller's HIP stream given to
+ *    mcd_init; functions marked "async" return before the work completes.
+ *  - The library allocates its own device workspace in mcd_init / mcd_bin
+ *    (hipMalloc) and frees it in mcd_free.
+ *  - Every function returns an mcd_status; no C++ exception crosses the ABI.
+ *    After an error, mcd_last_error(ctx) describes it.  Kernels that detect
+ *    an anomaly (a NaN or infinite rate, a non-positive mass or volume) set a
+ *    sticky device flag that the next syncing call reports as MCD_EDEVICE.
+ *  - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef MCD_H
+#define MCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MCD_OK = 0,
+  MCD_EINVAL = -1,   /* invalid argument; nothing was enqueued */
+  MCD_ENOMEM = -2,   /* device allocation failed */
+  MCD_EHIP = -3,     /* a HIP runtime call failed */
+  MCD_ESTATE = -4,   /* call out of order (e.g. mcd_step before mcd_bin) */
+  MCD_EDEVICE = -5   /* a kernel set the sticky anomaly flag */
+} mcd_status;
+
+/* collision kernels */
+#define MCD_K_PHYSICAL 0 /* geometric cross-section x relative velocity */
+#define MCD_K_CONSTANT 1 /* K = k0 (Smoluchowski test kernel) */
+#define MCD_K_LINEAR 2   /* K = k0 (m_i + m_j) (Smoluchowski test kernel) */
+
+/* flags: relative-velocity sources added in quadrature (bits 0-4),
+ * transport processes (bits 8-11), collisions on (bit 12) */
+#define MCD_DV_BROWNIAN (1u << 0)
+#define MCD_DV_TURB (1u << 1)
+#define MCD_DV_RADIAL (1u << 2)
+#define MCD_DV_AZIMUTHAL (1u << 3)
+#define MCD_DV_SETTLING (1u << 4)
+#define MCD_TR_DRIFT (1u << 8)
+#define MCD_TR_SETTLE (1u << 9)
+#define MCD_TR_MIX_R (1u << 10)
+#define MCD_TR_MIX_Z (1u << 11)
+#define MCD_COAG (1u << 12)
+
+/* arithmetic of the rate matrix */
+#define MCD_FP64 0  /* rates, sums and masses in FP64 */
+#define MCD_MIXED 1 /* pair rates in FP32 (per-cell power-of-two scale);
+                       masses, prefix sums, row-sum state and time in FP64 */
+
+/* cell schedule of the collision kernel */
+#define MCD_SCHED_PLAIN 0   /* one one-wave workgroup per cell, launched per step */
+#define MCD_SCHED_BATCHED 1 /* one persistent launch: big cells largest-first on
+                               four-wave teams, small cells on single waves;
+                               multi-step loops replayed from a HIP graph */
+
+/* outcome codes (event log and statistics) */
+#define MCD_OUT_STICK 0
+#define MCD_OUT_ERODE 1        /* i is the larger body and loses mass */
+#define MCD_OUT_ERODED_SMALL 2 /* i is the small projectile: fragment draw up to m_i */
+#define MCD_OUT_FRAG 3
+
+#define MCD_GAS_FIELDS 6 /* per-cell gas record: V, rho_g, T, alpha, r_c, zeta = z_c/H */
+#define MCD_GEOM_FIELDS 5 /* per-cell geometry: r_lo, r_hi, z_lo, z_hi, V */
+#define MCD_MAX_COMP 8
+
+typedef struct {
+  double sigma_g0;      /* gas surface density at r_ref [g cm^-2] */
+  double T0;            /* temperature at r_ref [K] */
+  double p, q;          /* Sigma_g ~ r^-p, T ~ r^-q */
+  double alpha;         /* turbulence strength (adaptive grid) */
+  double v_frag;        /* fragmentation velocity [cm/s] */
+  double erosion_ratio; /* mass ratio at and above which a fast collision erodes */
+  double a_mono;        /* monomer radius [cm]; smallest mass m0 = 4/3 pi a_mono^3 rho_s */
+  double rho_s;         /* material density [g cm^-3] */
+  double mu;            /* mean molecular weight */
+  double m_star;        /* stellar mass [g] */
+  double r_ref;         /* reference radius of the power laws [cm] */
+  double dm_max;        /* grouping threshold: r_ij is divided by max(1, dm_max m_i/m_j) and
+                           a collision moves that many bodies of swarm j (0 = off) */
+  double erosion_chi;   /* eroded mass in units of the (grouped) impactor mass */
+  double r_in;          /* inner removal radius [cm] (disk mode) */
+  double r_col;         /* column radius [cm] (column mode) */
+  double k0;            /* coefficient of the test kernels */
+  int32_t kernel;       /* MCD_K_* */
+  int32_t n_r, n_z;     /* adaptive grid: radial zones x cells per zone */
+  int32_t column;       /* 1 = one column at r_col; swarm masses per unit area */
+  uint32_t flags;       /* MCD_DV_* | MCD_TR_* | MCD_COAG */
+  int32_t n_comp;       /* composition fractions per particle, 0..MCD_MAX_COMP */
+  uint64_t seed;        /* Philox4x32-10 key (low word, high word) */
+  int32_t precision;    /* MCD_FP64 | MCD_MIXED */
+  int32_t schedule;     /* MCD_SCHED_PLAIN | MCD_SCHED_BATCHED */
+} mcd_params;
+
+typedef struct {
+  int64_t n;            /* number of particles N; particle id = array index */
+  double *r;            /* [N] radius [cm]                      (read/write) */
+  double *z;            /* [N] height above the midplane, >= 0  (read/write) */
+  double *m;            /* [N] representative-particle mass [g] (read/write) */
+  const double *M;      /* [N] swarm mass [g]; never written    (read) */
+  uint8_t *active;      /* [N] 1 = in the grid                  (read/write) */
+  float *comp;          /* [n_comp][N] composition fractions, component-major, or NULL */
+} mcd_particles;
+
+typedef struct {
+  int32_t n_cells;
+  const int32_t *cell_start; /* [n_cells + 1] device; member ranges into order */
+  const int32_t *order;      /* [cell_start[n_cells]] device; particle indices, each cell's
+                                members in the order that defines cumulative rates */
+  const double *gas;         /* [n_cells][MCD_GAS_FIELDS] device */
+} mcd_cells;
+
+typedef struct {
+  int64_t events;           /* collisions performed since mcd_init */
+  int64_t outcomes[4];      /* by MCD_OUT_* */
+  int64_t steps;            /* global steps completed */
+  int64_t n_active;         /* active particles after the last binning */
+  double t_sim;             /* simulated time [s] */
+  uint32_t device_flags;    /* sticky anomaly bits (0 = none) */
+  int32_t n_cells;          /* cells of the current grid */
+  int32_t max_cell;         /* largest cell of the current grid */
+  int32_t pad;
+} mcd_stats;
+
+typedef struct mcd_ctx mcd_ctx;
+
+/* Create a context.  Validates params (MCD_EINVAL on NaN, non-positive
+ * physical constants, n_r*n_z > N in adaptive mode, n_comp out of range,
+ * comp == NULL with n_comp > 0), records the particle views and the stream
+ * (a hipStream_t; NULL = the null stream), and allocates the workspace.
+ * Makes no kernel launch.  *out is set only on MCD_OK. */
+mcd_status mcd_init(const mcd_params *params, const mcd_particles *particles, void *hip_stream,
+                    mcd_ctx **out);
+
+/* Bin particles into cells (paper, Summary: adaptive grid of equal-count
+ * cells).  explicit_or_null == NULL: adaptive binning of the active
+ * particles into n_r radial zones of equal count by rank of (r, index), each
+ * split into n_z cells of equal count by rank of (z, index), with the floor
+ * rule for uneven counts; members of a cell are listed by ascending (z,
+ * index); gas state at the cell centre from the power-law disk.  Async.
+ * Otherwise: use the caller's explicit cells (device arrays are copied;
+ * the call synchronises once to plan the schedule). */
+mcd_status mcd_bin(mcd_ctx *ctx, const mcd_cells *explicit_or_null);
+
+/* Rate matrix of one cell (test path): r_out[i*ld + j] = r_ij, the rate at
+ * which representative particle i collides with a body of swarm j, computed
+ * by the same code as the collision kernel in the context's precision and
+ * returned as FP64 (device pointer, n_c x n_c with leading dimension ld >=
+ * n_c); rowsum_out[i] = sum_j r_ij as the collision kernel starts from
+ * (device, may be NULL).  Synchronises.  MCD_EINVAL if cell is out of range. */
+mcd_status mcd_rates(mcd_ctx *ctx, int32_t cell, double *r_out, int64_t ld, double *rowsum_out);
+
+/* Advance n_steps global steps of length dt [s]: (re)bin when the grid is
+ * adaptive, collide every cell, transport.  Inside a cell, events run until
+ * the next waiting time would pass dt (dt > 0) and/or max_events_per_cell
+ * events are done (> 0); at least one limit must be set.  Async; the
+ * batched schedule replays a captured HIP graph when n_steps > 1. */
+mcd_status mcd_step(mcd_ctx *ctx, double dt, int64_t max_events_per_cell, int32_t n_steps);
+
+/* Copy the counters to the host (synchronises) and report the sticky
+ * device flag as MCD_EDEVICE. */
+mcd_status mcd_get_stats(mcd_ctx *ctx, mcd_stats *host_out);
+
+/* Copy the current grid into caller device buffers (any may be NULL):
+ * cell_start [n_cells+1] int32, order [n_active] int32, geom
+ * [n_cells][MCD_GEOM_FIELDS] double (adaptive grids only), gas
+ * [n_cells][MCD_GAS_FIELDS] double.  Synchronises. */
+mcd_status mcd_get_cells(mcd_ctx *ctx, int32_t *cell_start, int32_t *order, double *geom,
+                         double *gas);
+
+/* Record the first per_cell events of every cell in the following steps:
+ * device buffer of n_cells * per_cell records of four int32 (i, j, outcome,
+ * 0), cell-local indices.  buf == NULL disables logging. */
+mcd_status mcd_set_event_log(mcd_ctx *ctx, int32_t *buf, int64_t per_cell);
+
+/* Philox4x32-10 (Salmon et al., SC'11) on the device, for tests: out[4k..4k+3]
+ * = Philox(ctr[4k..4k+3], key).  ctr and out are device arrays of 4n uint32.
+ * Async on hip_stream. */
+mcd_status mcd_philox(const uint32_t *ctr, uint32_t key_lo, uint32_t key_hi, uint32_t *out,
+                      int64_t n, void *hip_stream);
+
+/* Human-readable description of the last error of ctx (never NULL). */
+const char *mcd_last_error(const mcd_ctx *ctx);
+
+/* Release the workspace and the context (synchronises the stream first). */
+void mcd_free(mcd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

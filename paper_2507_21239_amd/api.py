@@ -1,0 +1,160 @@
+"""Thin Python front end of libmcd.so: torch tensors hold device memory and
+give the HIP stream; every call goes straight through the C ABI."""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib
+
+_STREAM = None
+
+
+class MCDError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_lib.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _stream_handle(stream) -> int | None:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream or None
+
+
+def _dev(t: torch.Tensor, dtype: torch.dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    return t
+
+
+class Simulation:
+    """One context of the collision step over caller-owned particle tensors.
+
+    particles: dict of device tensors r, z, m, M (float64 [N]), active
+    (uint8 [N]) and optionally comp (float32 [n_comp, N]).
+    """
+
+    def __init__(self, params: dict, particles: dict, precision: str = "mixed",
+                 schedule: str = "batched", stream=None):
+        self.lib = _lib.load()
+        self.params = dict(params)
+        self.t = {k: _dev(particles[k], torch.float64, k) for k in ("r", "z", "m", "M")}
+        self.t["active"] = _dev(particles["active"], torch.uint8, "active")
+        comp = particles.get("comp")
+        if comp is not None:
+            self.t["comp"] = _dev(comp, torch.float32, "comp")
+        self.N = self.t["m"].numel()
+        self._p = _lib.make_params(params, precision, schedule)
+        self._parts = _lib.Particles(
+            self.N, self.t["r"].data_ptr(), self.t["z"].data_ptr(), self.t["m"].data_ptr(),
+            self.t["M"].data_ptr(), self.t["active"].data_ptr(),
+            self.t["comp"].data_ptr() if comp is not None else None)
+        self.stream = stream
+        ctx = C.c_void_p()
+        st = self.lib.mcd_init(C.byref(self._p), C.byref(self._parts), _stream_handle(stream),
+                               C.byref(ctx))
+        if st != 0:
+            raise MCDError(st, "mcd_init rejected the parameters or particles")
+        self.ctx = ctx
+        self._keep = []
+
+    def _check(self, st: int, what: str) -> None:
+        if st != 0:
+            msg = self.lib.mcd_last_error(self.ctx)
+            raise MCDError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def bin(self, cells: dict | None = None) -> None:
+        if cells is None:
+            self._check(self.lib.mcd_bin(self.ctx, None), "mcd_bin")
+            return
+        cs = _dev(cells["cell_start"], torch.int32, "cell_start")
+        order = _dev(cells["order"], torch.int32, "order")
+        gas = _dev(cells["gas"], torch.float64, "gas")
+        c = _lib.Cells(cs.numel() - 1, cs.data_ptr(), order.data_ptr(), gas.data_ptr())
+        self._check(self.lib.mcd_bin(self.ctx, C.byref(c)), "mcd_bin")
+
+    def step(self, dt: float, max_events: int = 0, n_steps: int = 1) -> None:
+        self._check(self.lib.mcd_step(self.ctx, float(dt), int(max_events), int(n_steps)), "mcd_step")
+
+    def rates(self, cell: int, n: int) -> tuple[torch.Tensor, torch.Tensor]:
+        out = torch.empty((max(n, 1), max(n, 1)), dtype=torch.float64, device=self.t["m"].device)
+        rs = torch.empty(max(n, 1), dtype=torch.float64, device=self.t["m"].device)
+        self._check(self.lib.mcd_rates(self.ctx, int(cell), out.data_ptr(), out.shape[1],
+                                       rs.data_ptr()), "mcd_rates")
+        return out[:n, :n], rs[:n]
+
+    def stats(self, check: bool = True) -> dict:
+        s = _lib.Stats()
+        st = self.lib.mcd_get_stats(self.ctx, C.byref(s))
+        if check:
+            self._check(st, "mcd_get_stats")
+        return dict(events=s.events, outcomes=list(s.outcomes), steps=s.steps,
+                    n_active=s.n_active, t_sim=s.t_sim, device_flags=s.device_flags,
+                    n_cells=s.n_cells, max_cell=s.max_cell, status=st)
+
+    def cells(self) -> dict:
+        s = self.stats(check=False)
+        nc = s["n_cells"]
+        dev = self.t["m"].device
+        cs = torch.empty(nc + 1, dtype=torch.int32, device=dev)
+        self._check(self.lib.mcd_get_cells(self.ctx, cs.data_ptr(), None, None, None), "mcd_get_cells")
+        na = int(cs[-1].item())
+        order = torch.empty(max(na, 1), dtype=torch.int32, device=dev)
+        geom = torch.empty((nc, _lib.GEOM_FIELDS), dtype=torch.float64, device=dev)
+        gas = torch.empty((nc, _lib.GAS_FIELDS), dtype=torch.float64, device=dev)
+        self._check(self.lib.mcd_get_cells(self.ctx, cs.data_ptr(), order.data_ptr(),
+                                           geom.data_ptr(), gas.data_ptr()), "mcd_get_cells")
+        return dict(cell_start=cs, order=order[:na], geom=geom, gas=gas)
+
+    def set_event_log(self, buf: torch.Tensor | None, per_cell: int = 0) -> None:
+        if buf is None:
+            self._check(self.lib.mcd_set_event_log(self.ctx, None, 0), "mcd_set_event_log")
+            return
+        _dev(buf, torch.int32, "event log")
+        self._keep.append(buf)
+        self._check(self.lib.mcd_set_event_log(self.ctx, buf.data_ptr(), int(per_cell)),
+                    "mcd_set_event_log")
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None):
+            self.lib.mcd_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def philox(ctr: torch.Tensor, key: int, stream=None) -> torch.Tensor:
+    """Philox4x32-10 words on the device; ctr: int32 tensor [n, 4] (bit patterns)."""
+    lib = _lib.load()
+    ctr = _dev(ctr, torch.int32, "ctr")
+    out = torch.empty_like(ctr)
+    st = lib.mcd_philox(ctr.data_ptr(), key & 0xFFFFFFFF, (key >> 32) & 0xFFFFFFFF,
+                        out.data_ptr(), ctr.shape[0], _stream_handle(stream))
+    if st != 0:
+        raise MCDError(st, "mcd_philox")
+    return out
+
+
+def to_device(part: dict, device="cuda") -> dict:
+    """Copy a host particle dict (numpy arrays) to device tensors."""
+    out = {}
+    for k in ("r", "z", "m", "M"):
+        out[k] = torch.as_tensor(part[k], dtype=torch.float64).to(device).contiguous()
+    out["active"] = torch.as_tensor(part["active"], dtype=torch.uint8).to(device).contiguous()
+    if part.get("comp") is not None:
+        out["comp"] = torch.as_tensor(part["comp"], dtype=torch.float32).to(device).contiguous()
+    return out
+
+
+def cells_to_device(cells: dict, device="cuda") -> dict:
+    return dict(
+        cell_start=torch.as_tensor(cells["cell_start"], dtype=torch.int32).to(device).contiguous(),
+        order=torch.as_tensor(cells["order"], dtype=torch.int32).to(device).contiguous(),
+        gas=torch.as_tensor(cells["gas"], dtype=torch.float64).to(device).contiguous())

@@ -1,0 +1,523 @@
+// capi.hip -- the C ABI declared in include/mcd.h: argument validation,
+// workspace, cell schedules, the step loop and its HIP-graph replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "mcd.h"
+
+using namespace mcd;
+
+struct mcd_ctx {
+  mcd_params prm{};
+  Model model{};
+  mcd_particles part{};
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  bool adaptive = false, have_cells = false;
+  int32_t n_cells = 0, max_cell = 0, cells_alloc = 0;
+  int64_t order_alloc = 0;
+  int32_t *d_cell_start = nullptr, *d_order = nullptr, *d_big = nullptr, *d_small = nullptr;
+  double *d_gas = nullptr, *d_geom = nullptr;
+  int n_big = 0, n_small = 0, big_cap = 0, small_cap = 0;
+  std::vector<int32_t> h_cell_start;  // explicit grids
+  BinBuffers bb{};
+  DevState *d_state = nullptr;
+  int32_t *evlog = nullptr;
+  int64_t log_per_cell = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool g_valid = false;
+  double g_dt = 0.0;
+  int64_t g_max = 0;
+  std::string err;
+};
+
+namespace {
+
+constexpr int kSmallMax = 256;        // cells up to this size run on one wave
+constexpr int kBigMax = 2048;         // largest cell of the batched schedule
+constexpr int kPlainMax = 1024;       // largest cell of the plain schedule
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
+constexpr uint32_t kKnownFlags = DV_BROWNIAN | DV_TURB | DV_RADIAL | DV_AZIMUTHAL | DV_SETTLING |
+                                 TR_DRIFT | TR_SETTLE | TR_MIX_R | TR_MIX_Z | COAG;
+
+mcd_status fail(mcd_ctx *c, mcd_status s, const std::string &msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+mcd_status hip_fail(mcd_ctx *c, hipError_t e, const char *what) {
+  return fail(c, MCD_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define MCD_HIP(c, expr)                                \
+  do {                                                  \
+    hipError_t _e = (expr);                             \
+    if (_e != hipSuccess) return hip_fail(c, _e, #expr); \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void **)p, count * sizeof(T));
+}
+
+void dfree(void *p) {
+  if (p) (void)hipFree(p);
+}
+
+bool pos_finite(double x) { return std::isfinite(x) && x > 0.0; }
+
+std::string check_params(const mcd_params &p) {
+  const struct {
+    const char *name;
+    double v;
+  } positive[] = {{"sigma_g0", p.sigma_g0}, {"T0", p.T0}, {"a_mono", p.a_mono},
+                  {"rho_s", p.rho_s},       {"mu", p.mu}, {"m_star", p.m_star},
+                  {"r_ref", p.r_ref},       {"v_frag", p.v_frag}};
+  for (const auto &f : positive)
+    if (!pos_finite(f.v)) return std::string(f.name) + " must be finite and > 0";
+  if (!std::isfinite(p.p) || !std::isfinite(p.q)) return "p and q must be finite";
+  if (!(std::isfinite(p.alpha) && p.alpha >= 0.0)) return "alpha must be finite and >= 0";
+  if (!(std::isfinite(p.erosion_ratio) && p.erosion_ratio >= 1.0)) return "erosion_ratio must be >= 1";
+  if (!(std::isfinite(p.dm_max) && p.dm_max >= 0.0 && p.dm_max < 1.0)) return "dm_max must be in [0, 1)";
+  if (!(std::isfinite(p.erosion_chi) && p.erosion_chi >= 0.0)) return "erosion_chi must be >= 0";
+  if (!(std::isfinite(p.r_in) && p.r_in >= 0.0)) return "r_in must be >= 0";
+  if (!(std::isfinite(p.k0) && p.k0 >= 0.0)) return "k0 must be >= 0";
+  if (p.column && !pos_finite(p.r_col)) return "r_col must be > 0 in column mode";
+  if (p.kernel < MCD_K_PHYSICAL || p.kernel > MCD_K_LINEAR) return "unknown kernel";
+  if (p.n_r < 1 || p.n_z < 1) return "n_r and n_z must be >= 1";
+  if ((int64_t)p.n_r * p.n_z > (1 << 24)) return "too many cells";
+  if (p.flags & ~kKnownFlags) return "unknown flag bits";
+  if (p.n_comp < 0 || p.n_comp > MCD_MAX_COMP) return "n_comp must be in [0, 8]";
+  if (p.precision != MCD_FP64 && p.precision != MCD_MIXED) return "unknown precision";
+  if (p.schedule != MCD_SCHED_PLAIN && p.schedule != MCD_SCHED_BATCHED) return "unknown schedule";
+  return "";
+}
+
+Model make_model(const mcd_params &p) {
+  Model m{};
+  m.sigma_g0 = p.sigma_g0;
+  m.T0 = p.T0;
+  m.p = p.p;
+  m.q = p.q;
+  m.alpha = p.alpha;
+  m.v_frag = p.v_frag;
+  m.erosion_ratio = p.erosion_ratio;
+  m.rho_s = p.rho_s;
+  m.mu = p.mu;
+  m.m_star = p.m_star;
+  m.r_ref = p.r_ref;
+  m.dm_max = p.dm_max;
+  m.erosion_chi = p.erosion_chi;
+  m.r_in = p.r_in;
+  m.r_col = p.r_col;
+  m.k0 = p.k0;
+  m.m0 = 4.0 / 3.0 * kPi * p.a_mono * p.a_mono * p.a_mono * p.rho_s;  // monomer mass
+  m.flags = p.flags;
+  m.kernel = p.kernel;
+  m.column = p.column;
+  m.n_comp = p.n_comp;
+  m.key0 = (uint32_t)p.seed;
+  m.key1 = (uint32_t)(p.seed >> 32);
+  return m;
+}
+
+void drop_graph(mcd_ctx *c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->g_valid = false;
+}
+
+void free_grid(mcd_ctx *c) {
+  dfree(c->d_cell_start);
+  dfree(c->d_order);
+  dfree(c->d_gas);
+  dfree(c->d_geom);
+  dfree(c->d_big);
+  dfree(c->d_small);
+  c->d_cell_start = c->d_order = c->d_big = c->d_small = nullptr;
+  c->d_gas = c->d_geom = nullptr;
+  c->cells_alloc = 0;
+  c->order_alloc = 0;
+}
+
+mcd_status alloc_grid(mcd_ctx *c, int32_t n_cells, int64_t n_order) {
+  if (n_cells <= c->cells_alloc && n_order <= c->order_alloc) return MCD_OK;
+  free_grid(c);
+  if (dalloc(&c->d_cell_start, (size_t)n_cells + 1) != hipSuccess ||
+      dalloc(&c->d_order, (size_t)n_order) != hipSuccess ||
+      dalloc(&c->d_gas, (size_t)n_cells * MCD_GAS_FIELDS) != hipSuccess ||
+      dalloc(&c->d_geom, (size_t)n_cells * MCD_GEOM_FIELDS) != hipSuccess ||
+      dalloc(&c->d_big, (size_t)n_cells) != hipSuccess ||
+      dalloc(&c->d_small, (size_t)n_cells) != hipSuccess) {
+    free_grid(c);
+    return fail(c, MCD_ENOMEM, "device allocation of the grid failed");
+  }
+  c->cells_alloc = n_cells;
+  c->order_alloc = n_order;
+  return MCD_OK;
+}
+
+mcd_status alloc_binning(mcd_ctx *c, int64_t N) {
+  if (c->bb.cap >= N) return MCD_OK;
+  BinBuffers &b = c->bb;
+  const int tiles = radix_tiles(N);
+  if (dalloc(&b.keys[0], N) != hipSuccess || dalloc(&b.keys[1], N) != hipSuccess ||
+      dalloc(&b.vals[0], N) != hipSuccess || dalloc(&b.vals[1], N) != hipSuccess ||
+      dalloc(&b.by_r, N) != hipSuccess || dalloc(&b.zone, N) != hipSuccess ||
+      dalloc(&b.hist, (size_t)256 * tiles) != hipSuccess ||
+      dalloc(&b.digit_tot, 256) != hipSuccess)
+    return fail(c, MCD_ENOMEM, "device allocation of the binning workspace failed");
+  b.cap = N;
+  b.tiles = tiles;
+  return MCD_OK;
+}
+
+// cell lists of the batched schedule: big cells (team of four waves) and
+// small cells (one wave), each largest first; ties keep the cell index order
+mcd_status plan_lists(mcd_ctx *c, const std::vector<int32_t> &sizes) {
+  std::vector<int32_t> big, small;
+  int32_t mb = 0, ms = 0;
+  for (int32_t k = 0; k < (int32_t)sizes.size(); ++k) {
+    if (sizes[k] > kSmallMax) {
+      big.push_back(k);
+      mb = std::max(mb, sizes[k]);
+    } else if (sizes[k] > 0) {
+      small.push_back(k);
+      ms = std::max(ms, sizes[k]);
+    }
+  }
+  auto by_size = [&](int32_t a, int32_t b) { return sizes[a] > sizes[b]; };
+  std::stable_sort(big.begin(), big.end(), by_size);
+  std::stable_sort(small.begin(), small.end(), by_size);
+  c->n_big = (int)big.size();
+  c->n_small = (int)small.size();
+  c->big_cap = mb > 0 ? (mb + 255) / 256 * 256 : 0;
+  c->small_cap = std::max(64, (ms + 63) / 64 * 64);
+  c->max_cell = std::max(mb, ms);
+  if (c->prm.schedule == MCD_SCHED_PLAIN) c->small_cap = std::max(64, (c->max_cell + 63) / 64 * 64);
+  const size_t lds = c->prm.precision == MCD_FP64 ? region_bytes<double>(c->big_cap, 4)
+                                                   : region_bytes<float>(c->big_cap, 4);
+  const size_t lds_small = c->prm.precision == MCD_FP64
+                               ? region_bytes<double>(c->small_cap, 1) *
+                                     (c->prm.schedule == MCD_SCHED_PLAIN ? 1 : 4)
+                               : region_bytes<float>(c->small_cap, 1) *
+                                     (c->prm.schedule == MCD_SCHED_PLAIN ? 1 : 4);
+  if (std::max(lds, lds_small) > kLdsBytes)
+    return fail(c, MCD_EINVAL, "largest cell does not fit the 160 KB LDS in this precision");
+  if (!big.empty())
+    MCD_HIP(c, hipMemcpy(c->d_big, big.data(), big.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (!small.empty())
+    MCD_HIP(c, hipMemcpy(c->d_small, small.data(), small.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice));
+  return MCD_OK;
+}
+
+CollideArgs collide_args(mcd_ctx *c, double dt, int64_t max_events) {
+  CollideArgs a{};
+  a.P = c->model;
+  a.cell_start = c->d_cell_start;
+  a.order = c->d_order;
+  a.gas = c->d_gas;
+  a.big_list = c->d_big;
+  a.small_list = c->d_small;
+  a.n_big = c->n_big;
+  a.n_small = c->n_small;
+  a.big_cap = c->big_cap;
+  a.small_cap = c->small_cap;
+  a.m = c->part.m;
+  a.M = c->part.M;
+  a.comp = c->part.comp;
+  a.N = c->part.n;
+  a.dt = dt;
+  a.max_events = max_events;
+  a.state = c->d_state;
+  a.evlog = c->evlog;
+  a.log_per_cell = c->log_per_cell;
+  return a;
+}
+
+bool transport_on(const mcd_ctx *c) {
+  return (c->prm.flags & (TR_DRIFT | TR_SETTLE | TR_MIX_R | TR_MIX_Z)) != 0;
+}
+
+mcd_status enqueue_bin(mcd_ctx *c, hipStream_t s) {
+  hipError_t e = launch_binning(c->model, c->prm.n_r, c->prm.n_z, c->part.r, c->part.z,
+                                c->part.active, c->part.n, c->bb, c->d_cell_start, c->d_order,
+                                c->d_geom, c->d_gas, c->d_state, s);
+  if (e != hipSuccess) return hip_fail(c, e, "binning");
+  return MCD_OK;
+}
+
+mcd_status enqueue_step(mcd_ctx *c, double dt, int64_t max_events, hipStream_t s) {
+  mcd_status st;
+  if (c->adaptive && (st = enqueue_bin(c, s)) != MCD_OK) return st;
+  if (c->prm.flags & COAG) {
+    hipError_t e = launch_collide(collide_args(c, dt, max_events), c->prm.precision,
+                                  c->prm.schedule, c->n_cells, c->max_cell, 0, s);
+    if (e != hipSuccess) return hip_fail(c, e, "collide");
+  }
+  if (c->adaptive && transport_on(c)) {
+    hipError_t e = launch_transport(c->model, c->part.r, c->part.z, c->part.m, c->part.active,
+                                    c->part.n, dt, c->d_state, s);
+    if (e != hipSuccess) return hip_fail(c, e, "transport");
+  }
+  hipError_t e = launch_finish_step(c->d_state, dt, s);
+  if (e != hipSuccess) return hip_fail(c, e, "finish_step");
+  return MCD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mcd_status mcd_init(const mcd_params *params, const mcd_particles *particles, void *hip_stream,
+                    mcd_ctx **out) {
+  if (!params || !particles || !out) return MCD_EINVAL;
+  std::string why = check_params(*params);
+  const mcd_particles &p = *particles;
+  if (why.empty()) {
+    if (p.n <= 0 || p.n >= (int64_t)1 << 31) why = "particle count must be in [1, 2^31)";
+    else if (!p.r || !p.z || !p.m || !p.M || !p.active) why = "particle arrays must not be NULL";
+    else if (params->n_comp > 0 && !p.comp) why = "comp must be given when n_comp > 0";
+  }
+  if (!why.empty()) return MCD_EINVAL;
+  mcd_ctx *c = new (std::nothrow) mcd_ctx();
+  if (!c) return MCD_ENOMEM;
+  c->prm = *params;
+  c->model = make_model(*params);
+  c->part = p;
+  if (params->n_comp == 0) c->part.comp = nullptr;
+  c->stream = (hipStream_t)hip_stream;
+  hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMalloc((void **)&c->d_state, sizeof(DevState));
+  if (e == hipSuccess) e = hipMemset(c->d_state, 0, sizeof(DevState));
+  if (e != hipSuccess) {
+    mcd_free(c);
+    return e == hipErrorOutOfMemory ? MCD_ENOMEM : MCD_EHIP;
+  }
+  *out = c;
+  return MCD_OK;
+}
+
+mcd_status mcd_bin(mcd_ctx *c, const mcd_cells *cells) {
+  if (!c) return MCD_EINVAL;
+  drop_graph(c);
+  if (!cells) {
+    const int64_t N = c->part.n;
+    const int nr = c->prm.n_r, nz = c->prm.n_z;
+    if ((int64_t)nr * nz > N) return fail(c, MCD_EINVAL, "n_r * n_z exceeds the particle count");
+    const int64_t zone_max = (N + nr - 1) / nr;
+    const int32_t cell_max = (int32_t)((zone_max + nz - 1) / nz);
+    const int32_t limit = c->prm.schedule == MCD_SCHED_PLAIN ? kPlainMax : kBigMax;
+    if (cell_max > limit)
+      return fail(c, MCD_EINVAL, "cells would exceed " + std::to_string(limit) +
+                                     " particles; use more cells");
+    mcd_status st;
+    if ((st = alloc_grid(c, nr * nz, N)) != MCD_OK) return st;
+    if ((st = alloc_binning(c, N)) != MCD_OK) return st;
+    c->adaptive = true;
+    c->n_cells = nr * nz;
+    // equal-count cells differ by at most one particle: a single class
+    std::vector<int32_t> sizes((size_t)c->n_cells, cell_max);
+    if ((st = plan_lists(c, sizes)) != MCD_OK) return st;
+    if ((st = enqueue_bin(c, c->stream)) != MCD_OK) return st;
+    c->have_cells = true;
+    return MCD_OK;
+  }
+  // explicit cells
+  const int32_t nc = cells->n_cells;
+  if (nc < 1 || !cells->cell_start || !cells->order || !cells->gas)
+    return fail(c, MCD_EINVAL, "explicit cells need n_cells >= 1 and device arrays");
+  std::vector<int32_t> cs((size_t)nc + 1);
+  MCD_HIP(c, hipMemcpy(cs.data(), cells->cell_start, cs.size() * sizeof(int32_t),
+                       hipMemcpyDeviceToHost));
+  if (cs[0] < 0) return fail(c, MCD_EINVAL, "cell_start[0] < 0");
+  std::vector<int32_t> sizes((size_t)nc);
+  for (int32_t k = 0; k < nc; ++k) {
+    sizes[k] = cs[k + 1] - cs[k];
+    if (sizes[k] < 0) return fail(c, MCD_EINVAL, "cell_start must be non-decreasing");
+  }
+  const int64_t n_order = cs[nc];
+  std::vector<int32_t> ord((size_t)std::max<int64_t>(n_order, 1));
+  if (n_order > 0)
+    MCD_HIP(c, hipMemcpy(ord.data(), cells->order, (size_t)n_order * sizeof(int32_t),
+                         hipMemcpyDeviceToHost));
+  for (int64_t k = cs[0]; k < n_order; ++k)
+    if (ord[k] < 0 || ord[k] >= c->part.n) return fail(c, MCD_EINVAL, "order index out of range");
+  const int32_t mx = sizes.empty() ? 0 : *std::max_element(sizes.begin(), sizes.end());
+  const int32_t limit = c->prm.schedule == MCD_SCHED_PLAIN ? kPlainMax : kBigMax;
+  if (mx > limit)
+    return fail(c, MCD_EINVAL, "a cell exceeds " + std::to_string(limit) + " particles");
+  mcd_status st;
+  if ((st = alloc_grid(c, nc, std::max<int64_t>(n_order, 1))) != MCD_OK) return st;
+  MCD_HIP(c, hipMemcpyAsync(c->d_cell_start, cells->cell_start, cs.size() * sizeof(int32_t),
+                            hipMemcpyDeviceToDevice, c->stream));
+  if (n_order > 0)
+    MCD_HIP(c, hipMemcpyAsync(c->d_order, cells->order, (size_t)n_order * sizeof(int32_t),
+                              hipMemcpyDeviceToDevice, c->stream));
+  MCD_HIP(c, hipMemcpyAsync(c->d_gas, cells->gas, (size_t)nc * MCD_GAS_FIELDS * sizeof(double),
+                            hipMemcpyDeviceToDevice, c->stream));
+  MCD_HIP(c, hipStreamSynchronize(c->stream));
+  c->adaptive = false;
+  c->n_cells = nc;
+  c->h_cell_start = cs;
+  if ((st = plan_lists(c, sizes)) != MCD_OK) return st;
+  c->have_cells = true;
+  return MCD_OK;
+}
+
+mcd_status mcd_rates(mcd_ctx *c, int32_t cell, double *r_out, int64_t ld, double *rowsum_out) {
+  if (!c) return MCD_EINVAL;
+  if (!c->have_cells) return fail(c, MCD_ESTATE, "mcd_rates before mcd_bin");
+  if (cell < 0 || cell >= c->n_cells || !r_out) return fail(c, MCD_EINVAL, "bad cell or r_out");
+  int32_t se[2];
+  MCD_HIP(c, hipMemcpyAsync(se, c->d_cell_start + cell, 2 * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, c->stream));
+  MCD_HIP(c, hipStreamSynchronize(c->stream));
+  if (ld < se[1] - se[0]) return fail(c, MCD_EINVAL, "ld smaller than the cell size");
+  hipError_t e = launch_rates_cell(collide_args(c, 0.0, 0), c->prm.precision, cell, r_out, ld,
+                                   rowsum_out, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "rates");
+  MCD_HIP(c, hipStreamSynchronize(c->stream));
+  return MCD_OK;
+}
+
+mcd_status mcd_step(mcd_ctx *c, double dt, int64_t max_events, int32_t n_steps) {
+  if (!c) return MCD_EINVAL;
+  if (!c->have_cells) return fail(c, MCD_ESTATE, "mcd_step before mcd_bin");
+  if (!(std::isfinite(dt) && dt >= 0.0) || max_events < 0 || n_steps < 0)
+    return fail(c, MCD_EINVAL, "dt, max_events and n_steps must be >= 0");
+  if (!(dt > 0.0) && max_events == 0)
+    return fail(c, MCD_EINVAL, "set a time limit dt > 0 or max_events > 0");
+  if (max_events >= ((int64_t)1 << 32)) return fail(c, MCD_EINVAL, "max_events must be < 2^32");
+  if (c->adaptive && transport_on(c) && !(dt > 0.0))
+    return fail(c, MCD_EINVAL, "transport needs dt > 0");
+  if (n_steps == 0) return MCD_OK;
+  const bool use_graph = c->prm.schedule == MCD_SCHED_BATCHED && n_steps > 1;
+  if (!use_graph) {
+    for (int32_t k = 0; k < n_steps; ++k) {
+      mcd_status st = enqueue_step(c, dt, max_events, c->stream);
+      if (st != MCD_OK) return st;
+    }
+    return MCD_OK;
+  }
+  if (!c->g_valid || c->g_dt != dt || c->g_max != max_events) {
+    drop_graph(c);
+    MCD_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    mcd_status st = enqueue_step(c, dt, max_events, c->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (st != MCD_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+    c->graph = g;
+    MCD_HIP(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    c->g_valid = true;
+    c->g_dt = dt;
+    c->g_max = max_events;
+  }
+  for (int32_t k = 0; k < n_steps; ++k) MCD_HIP(c, hipGraphLaunch(c->gexec, c->stream));
+  return MCD_OK;
+}
+
+mcd_status mcd_get_stats(mcd_ctx *c, mcd_stats *o) {
+  if (!c || !o) return MCD_EINVAL;
+  DevState s{};
+  MCD_HIP(c, hipMemcpyAsync(&s, c->d_state, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+  MCD_HIP(c, hipStreamSynchronize(c->stream));
+  std::memset(o, 0, sizeof(*o));
+  o->events = (int64_t)s.events;
+  for (int k = 0; k < 4; ++k) o->outcomes[k] = (int64_t)s.outcomes[k];
+  o->steps = s.step;
+  o->n_active = c->adaptive ? s.n_active : (c->have_cells ? c->h_cell_start.back() : 0);
+  o->t_sim = s.t_sim;
+  o->device_flags = s.flags;
+  o->n_cells = c->n_cells;
+  o->max_cell = c->max_cell;
+  if (s.flags) {
+    c->err = "device anomaly flags 0x" + std::to_string(s.flags);
+    return MCD_EDEVICE;
+  }
+  return MCD_OK;
+}
+
+mcd_status mcd_get_cells(mcd_ctx *c, int32_t *cell_start, int32_t *order, double *geom,
+                         double *gas) {
+  if (!c) return MCD_EINVAL;
+  if (!c->have_cells) return fail(c, MCD_ESTATE, "no grid yet");
+  int32_t n_order = 0;
+  MCD_HIP(c, hipMemcpyAsync(&n_order, c->d_cell_start + c->n_cells, sizeof(int32_t),
+                            hipMemcpyDeviceToHost, c->stream));
+  MCD_HIP(c, hipStreamSynchronize(c->stream));
+  const size_t nc = (size_t)c->n_cells;
+  if (cell_start)
+    MCD_HIP(c, hipMemcpyAsync(cell_start, c->d_cell_start, (nc + 1) * sizeof(int32_t),
+                              hipMemcpyDeviceToDevice, c->stream));
+  if (order && n_order > 0)
+    MCD_HIP(c, hipMemcpyAsync(order, c->d_order, (size_t)n_order * sizeof(int32_t),
+                              hipMemcpyDeviceToDevice, c->stream));
+  if (geom && c->adaptive)
+    MCD_HIP(c, hipMemcpyAsync(geom, c->d_geom, nc * MCD_GEOM_FIELDS * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
+  if (gas)
+    MCD_HIP(c, hipMemcpyAsync(gas, c->d_gas, nc * MCD_GAS_FIELDS * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
+  MCD_HIP(c, hipStreamSynchronize(c->stream));
+  return MCD_OK;
+}
+
+mcd_status mcd_set_event_log(mcd_ctx *c, int32_t *buf, int64_t per_cell) {
+  if (!c) return MCD_EINVAL;
+  if (buf && per_cell <= 0) return fail(c, MCD_EINVAL, "per_cell must be > 0");
+  c->evlog = buf;
+  c->log_per_cell = buf ? per_cell : 0;
+  drop_graph(c);
+  return MCD_OK;
+}
+
+mcd_status mcd_philox(const uint32_t *ctr, uint32_t key_lo, uint32_t key_hi, uint32_t *out,
+                      int64_t n, void *hip_stream) {
+  if (n < 0 || (n > 0 && (!ctr || !out))) return MCD_EINVAL;
+  hipError_t e = launch_philox(ctr, key_lo, key_hi, out, n, (hipStream_t)hip_stream);
+  return e == hipSuccess ? MCD_OK : MCD_EHIP;
+}
+
+const char *mcd_last_error(const mcd_ctx *c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+void mcd_free(mcd_ctx *c) {
+  if (!c) return;
+  if (c->stream || c->d_state) (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
+  free_grid(c);
+  BinBuffers &b = c->bb;
+  dfree(b.keys[0]);
+  dfree(b.keys[1]);
+  dfree(b.vals[0]);
+  dfree(b.vals[1]);
+  dfree(b.by_r);
+  dfree(b.zone);
+  dfree(b.hist);
+  dfree(b.digit_tot);
+  dfree(c->d_state);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  delete c;
+}
+
+}  // extern "C"

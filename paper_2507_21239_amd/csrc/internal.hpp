@@ -1,0 +1,88 @@
+// internal.hpp -- launch arguments and device state shared by the kernels
+// and the C-ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "physics.hpp"
+
+namespace mcd {
+
+// device-resident state: everything a replayed graph must see change
+struct DevState {
+  uint32_t step;          // global step index (Philox counter word 2)
+  uint32_t flags;         // sticky anomaly bits
+  int32_t n_active;       // active particles after binning
+  int32_t big_head;       // persistent work queues
+  int32_t small_head;
+  int32_t pad0;
+  double t_sim;           // simulated time
+  unsigned long long events;
+  unsigned long long outcomes[4];
+};
+
+enum : uint32_t {
+  FLAG_BAD_RATE = 1u << 0,   // NaN / inf rate sum
+  FLAG_BAD_MASS = 1u << 1,   // non-positive or non-finite mass produced
+  FLAG_BAD_VOLUME = 1u << 2, // non-positive cell volume with members
+  FLAG_CAPACITY = 1u << 3,   // cell larger than the launch's capacity
+};
+
+struct CollideArgs {
+  Model P;
+  const int32_t *cell_start;
+  const int32_t *order;
+  const double *gas;        // [n_cells][6]
+  const int32_t *big_list;  // cells processed by four-wave teams, largest first
+  const int32_t *small_list;// cells processed by single waves, largest first
+  int32_t n_big, n_small;
+  int32_t big_cap, small_cap;   // particle capacity of a team's LDS region
+  double *m;
+  const double *M;
+  float *comp;
+  int64_t N;
+  double dt;
+  int64_t max_events;
+  DevState *state;
+  int32_t *evlog;
+  int64_t log_per_cell;
+};
+
+// LDS bytes of one team region holding `cap` particles
+template <typename RT>
+constexpr size_t region_bytes(int cap, int T) {
+  // ten RT arrays + m, M (double) + index (int) + team scratch
+  return (size_t)cap * (10 * sizeof(RT) + 2 * sizeof(double) + sizeof(int32_t)) + 64 * T + 64;
+}
+
+// launchers (collide.hip)
+hipError_t launch_collide(const CollideArgs &a, int precision, int schedule, int n_cells,
+                          int max_cell, int grid_override, hipStream_t s);
+hipError_t launch_rates_cell(const CollideArgs &a, int precision, int cell, double *r_out,
+                             int64_t ld, double *rowsum_out, hipStream_t s);
+// transport (transport.hip)
+hipError_t launch_transport(const Model &P, double *r, double *z, const double *m,
+                            uint8_t *active, int64_t N, double dt, DevState *state,
+                            hipStream_t s);
+hipError_t launch_finish_step(DevState *state, double dt, hipStream_t s);
+hipError_t launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t n,
+                         hipStream_t s);
+
+// binning (binning.hip)
+struct BinBuffers {
+  uint64_t *keys[2];
+  int32_t *vals[2];
+  int32_t *by_r;       // active particle indices by ascending (r, index)
+  int32_t *zone;       // zone of every particle (n_r for inactive)
+  uint32_t *hist;      // radix histogram [256][tiles]
+  uint32_t *digit_tot; // [256]
+  int64_t cap;         // particles
+  int32_t tiles;
+};
+hipError_t launch_binning(const Model &P, int n_r, int n_z, const double *r, const double *z,
+                          const uint8_t *active, int64_t N, BinBuffers &b, int32_t *cell_start,
+                          int32_t *order, double *geom, double *gas, DevState *state,
+                          hipStream_t s);
+int radix_tiles(int64_t n);
+
+}  // namespace mcd

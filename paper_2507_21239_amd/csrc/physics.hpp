@@ -1,0 +1,284 @@
+// physics.hpp -- gas state, particle state and the pair collision rate of
+// the representative-particle method, for device (and host) code.
+//
+// The paper (arXiv 2507.21239, Summary) fixes the model: a static
+// power-law disk, vertically isothermal; representative particles after
+// Zsom & Dullemond (2008) colliding inside equal-count cells; relative
+// velocities from Brownian motion, turbulence, radial and azimuthal drift and
+// settling (the formulas are deferred to Drazkowska et al. 2013).  The forms
+// used here: thin-disk gas (Gaussian vertical profile), Epstein / Stokes
+// drag switching at a = 9 lambda / 4, Nakagawa-type drift velocities,
+// turbulent velocities in the three closed-form regimes of Ormel & Cuzzi
+// (2007), the five sources added in quadrature, geometric cross-sections,
+// and the swarm rate r_ij = n_j K_ij / max(1, dm_max m_i / m_j).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace mcd {
+
+// physical constants, CGS
+constexpr double kBoltz = 1.380649e-16;
+constexpr double kMassH = 1.6735575e-24;
+constexpr double kGrav = 6.67430e-8;
+constexpr double kSigmaH2 = 2e-15;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kYa = 1.6;  // Ormel & Cuzzi (2007) y*_a
+
+enum : uint32_t {
+  DV_BROWNIAN = 1u << 0,
+  DV_TURB = 1u << 1,
+  DV_RADIAL = 1u << 2,
+  DV_AZIMUTHAL = 1u << 3,
+  DV_SETTLING = 1u << 4,
+  TR_DRIFT = 1u << 8,
+  TR_SETTLE = 1u << 9,
+  TR_MIX_R = 1u << 10,
+  TR_MIX_Z = 1u << 11,
+  COAG = 1u << 12,
+};
+enum { K_PHYSICAL = 0, K_CONSTANT = 1, K_LINEAR = 2 };
+enum { OUT_STICK = 0, OUT_ERODE = 1, OUT_ERODED_SMALL = 2, OUT_FRAG = 3 };
+
+// model constants copied to the device by value
+struct Model {
+  double sigma_g0, T0, p, q, alpha, v_frag, erosion_ratio, rho_s, mu, m_star, r_ref;
+  double dm_max, erosion_chi, r_in, r_col, k0, m0;
+  uint32_t flags;
+  int32_t kernel, column, n_comp;
+  uint32_t key0, key1;
+};
+
+// gas state of a cell, from its six primaries (V, rho_g, T, alpha, r_c,
+// zeta = z_c / H)
+struct Gas {
+  double V, rho_g, T, alpha, r_c, zeta;
+  double cs, Omega, H, z_c, eta_vK, v_th, lambda, nu, Re, St_eta, Vg2;
+};
+
+__host__ __device__ inline void gas_from_primaries(const Model &P, const double *prim, Gas &g) {
+  g.V = prim[0];
+  g.rho_g = prim[1];
+  g.T = prim[2];
+  g.alpha = prim[3];
+  g.r_c = prim[4];
+  g.zeta = prim[5];
+  g.cs = sqrt(kBoltz * g.T / (P.mu * kMassH));
+  g.Omega = sqrt(kGrav * P.m_star / (g.r_c * g.r_c * g.r_c));
+  g.H = g.cs / g.Omega;
+  g.z_c = g.zeta * g.H;
+  // midplane pressure-gradient velocity: P ~ r^-(p + (q+3)/2)
+  g.eta_vK = 0.5 * (g.cs * g.cs) / (g.Omega * g.r_c) * (P.p + (P.q + 3.0) / 2.0);
+  g.v_th = sqrt(8.0 / kPi) * g.cs;
+  g.lambda = P.mu * kMassH / (g.rho_g * kSigmaH2);
+  g.nu = 0.5 * g.v_th * g.lambda;
+  g.Re = g.alpha * g.cs * g.H / g.nu;
+  g.St_eta = 1.0 / sqrt(g.Re);
+  g.Vg2 = 1.5 * g.alpha * g.cs * g.cs;
+}
+
+// power-law disk at (r, z): Sigma_g, T, c_s, Omega, H, rho_g
+struct DiskPoint {
+  double Sigma_g, T, cs, Omega, H, rho_g;
+};
+
+__host__ __device__ inline DiskPoint disk_at(const Model &P, double r, double z) {
+  DiskPoint d;
+  const double x = r / P.r_ref;
+  d.Sigma_g = P.sigma_g0 * pow(x, -P.p);
+  d.T = P.T0 * pow(x, -P.q);
+  d.cs = sqrt(kBoltz * d.T / (P.mu * kMassH));
+  d.Omega = sqrt(kGrav * P.m_star / (r * r * r));
+  d.H = d.cs / d.Omega;
+  d.rho_g = d.Sigma_g / (sqrt(2.0 * kPi) * d.H) * exp(-(z * z) / (2.0 * d.H * d.H));
+  return d;
+}
+
+__host__ __device__ inline double stopping_time(double rho_s, double a, double rho_g, double v_th,
+                                                double lambda, double nu) {
+  if (a < 2.25 * lambda) return rho_s * a / (rho_g * v_th);  // Epstein
+  return 2.0 * rho_s * a * a / (9.0 * nu * rho_g);           // Stokes
+}
+
+// per-particle record used by the pair rate, in the rate precision RT
+template <typename RT>
+struct Rec {
+  RT m;    // mass
+  RT im;   // 1/m
+  RT a;    // radius
+  RT St;   // Stokes number
+  RT h;    // St^2 / (St + St_eta)
+  RT q1;   // 1 / (1 + St)
+  RT vr;   // radial drift velocity
+  RT vp;   // azimuthal velocity relative to Keplerian
+  RT vz;   // settling velocity at the cell height
+  RT nd;   // swarm number density M/(m V), times the cell's rate scale
+};
+
+// particle state in FP64 (the precompute is always FP64), rounded to RT
+template <typename RT>
+__host__ __device__ inline Rec<RT> make_rec(const Model &P, const Gas &g, double m, double M,
+                                            double nd_scale) {
+  const double a = cbrt(3.0 * m / (4.0 * kPi * P.rho_s));
+  const double ts = stopping_time(P.rho_s, a, g.rho_g, g.v_th, g.lambda, g.nu);
+  const double St = ts * g.Omega;
+  Rec<RT> o;
+  o.m = (RT)m;
+  o.im = (RT)(1.0 / m);
+  o.a = (RT)a;
+  o.St = (RT)St;
+  o.h = (RT)(St * St / (St + g.St_eta));
+  o.q1 = (RT)(1.0 / (1.0 + St));
+  o.vr = (RT)(-2.0 * g.eta_vK * St / (1.0 + St * St));
+  o.vp = (RT)(-g.eta_vK / (1.0 + St * St));
+  o.vz = (RT)(-g.z_c * g.Omega * St / (1.0 + St));
+  o.nd = (RT)(M / (m * g.V) * nd_scale);
+  return o;
+}
+
+// per-cell constants of the pair rate
+template <typename RT>
+struct PairConst {
+  RT cBM;      // 8 k T / pi
+  RT Vg2;      // large-eddy velocity squared
+  RT St_eta;   // Kolmogorov Stokes number Re^-1/2
+  RT dm_max;
+  RT k0;
+  uint32_t flags;
+  int32_t kernel;
+};
+
+template <typename RT>
+__host__ __device__ inline PairConst<RT> make_pair_const(const Model &P, const Gas &g) {
+  PairConst<RT> c;
+  c.cBM = (RT)(8.0 * kBoltz * g.T / kPi);
+  c.Vg2 = (RT)g.Vg2;
+  c.St_eta = (RT)g.St_eta;
+  c.dm_max = (RT)P.dm_max;
+  c.k0 = (RT)P.k0;
+  c.flags = P.flags;
+  c.kernel = P.kernel;
+  return c;
+}
+
+// precision-specific division and square root: FP64 correctly rounded;
+// FP32 through the hardware reciprocal and square root (about 1 ulp)
+__device__ inline double pdiv(double a, double b) { return a / b; }
+__device__ inline float pdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ inline double prcp(double b) { return 1.0 / b; }
+__device__ inline float prcp(float b) { return __builtin_amdgcn_rcpf(b); }
+__device__ inline double psqrt(double x) { return sqrt(x); }
+__device__ inline float psqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// turbulent relative velocity squared (Ormel & Cuzzi 2007 closed forms)
+template <typename RT>
+__device__ inline RT dv2_turb(const PairConst<RT> &c, const Rec<RT> &x, const Rec<RT> &y) {
+  const bool xb = x.St > y.St;
+  const RT St1 = xb ? x.St : y.St, St2 = xb ? y.St : x.St;
+  if (St1 < c.St_eta) {
+    const RT h1 = xb ? x.h : y.h, h2 = xb ? y.h : x.h;
+    return pdiv(c.Vg2 * (St1 - St2), St1 + St2) * (h1 - h2);
+  }
+  if (St1 < (RT)1) {
+    const RT eps = pdiv(St2, St1);
+    const RT br = (RT)(2.0 * kYa) - ((RT)1 + eps) +
+                  pdiv((RT)2, (RT)1 + eps) *
+                      ((RT)(1.0 / (1.0 + kYa)) + pdiv(eps * eps * eps, (RT)kYa + eps));
+    return c.Vg2 * St1 * br;
+  }
+  return c.Vg2 * (x.q1 + y.q1);
+}
+
+// relative velocity of the pair (five sources in quadrature)
+template <typename RT>
+__device__ inline RT rel_velocity(const PairConst<RT> &c, const Rec<RT> &x, const Rec<RT> &y) {
+  RT dv2 = (RT)0;
+  if (c.flags & DV_BROWNIAN) dv2 += c.cBM * (x.im + y.im);
+  if (c.flags & DV_TURB) dv2 += dv2_turb(c, x, y);
+  if (c.flags & DV_RADIAL) {
+    const RT d = x.vr - y.vr;
+    dv2 += d * d;
+  }
+  if (c.flags & DV_AZIMUTHAL) {
+    const RT d = x.vp - y.vp;
+    dv2 += d * d;
+  }
+  if (c.flags & DV_SETTLING) {
+    const RT d = x.vz - y.vz;
+    dv2 += d * d;
+  }
+  return psqrt(dv2);
+}
+
+// symmetric collision kernel K_xy; dv receives the relative velocity
+template <typename RT>
+__device__ inline RT pair_kernel(const PairConst<RT> &c, const Rec<RT> &x, const Rec<RT> &y,
+                                 RT &dv) {
+  if (c.kernel == K_CONSTANT) {
+    dv = (RT)0;
+    return c.k0;
+  }
+  if (c.kernel == K_LINEAR) {
+    dv = (RT)0;
+    return c.k0 * (x.m + y.m);
+  }
+  dv = rel_velocity(c, x, y);
+  const RT s = x.a + y.a;
+  return (RT)kPi * s * s * dv;
+}
+
+// rate of representative particle x against swarm y given K_xy:
+// n_y K / max(1, dm_max m_x / m_y)
+template <typename RT>
+__device__ inline RT swarm_rate(const PairConst<RT> &c, const Rec<RT> &x, const Rec<RT> &y, RT K) {
+  RT r = y.nd * K;
+  if (c.dm_max > (RT)0) {
+    RT grp = pdiv(c.dm_max * x.m, y.m);
+    if (grp > (RT)1) r = pdiv(r, grp);
+  }
+  return r;
+}
+
+// fragment mass: inverse-CDF draw from the mass-weighted distribution
+// ~ m^(-5/6) (number slope 11/6) on [lo, hi]
+__host__ __device__ inline double frag_draw(double lo, double hi, double u) {
+  if (!(hi > lo)) return lo;
+  const double slo = sqrt(cbrt(lo)), shi = sqrt(cbrt(hi));
+  const double x = slo + u * (shi - slo);
+  const double x2 = x * x;
+  return x2 * x2 * x2;
+}
+
+// grouping factor max(1, dm_max m_i / m_j)
+__host__ __device__ inline double group_factor(double dm_max, double mi, double mj) {
+  if (!(dm_max > 0.0)) return 1.0;
+  const double g = dm_max * mi / mj;
+  return g < 1.0 ? 1.0 : g;
+}
+
+// collision outcome for representative particle i (mass mi) hitting a body
+// of swarm j (mass mj) at relative velocity dv; returns the outcome code
+__host__ __device__ inline int outcome(const Model &P, bool fast, double mi, double mj, double u,
+                                       double &m_new) {
+  const double grp = group_factor(P.dm_max, mi, mj);
+  if (P.kernel != K_PHYSICAL || !fast) {
+    m_new = mi + grp * mj;
+    return OUT_STICK;
+  }
+  const double big = mi > mj ? mi : mj;
+  const double small = mi > mj ? mj : mi;
+  if (big / small >= P.erosion_ratio) {
+    if (mi >= mj) {
+      const double m = mi - P.erosion_chi * grp * mj;
+      m_new = m > P.m0 ? m : P.m0;
+      return OUT_ERODE;
+    }
+    m_new = frag_draw(P.m0, mi, u);
+    return OUT_ERODED_SMALL;
+  }
+  m_new = frag_draw(P.m0, big, u);
+  return OUT_FRAG;
+}
+
+}  // namespace mcd

@@ -144,12 +144,18 @@ def c5_large_disk(seed: int = 0, N: int = 2_000_000, n_r: int = 1000, n_z: int =
 
 
 def c4_batched(seed: int = 0, n_cells: int = 4096, n_lo: int = 64, n_hi: int = 1024,
-               events: int = 1000, philox_seed: int = 0, V: float = 1e36) -> dict:
-    """Independent cells with log-uniform particle counts in [n_lo, n_hi],
-    log-uniform masses 1e-12 .. 1e2 g, random local gas (rho_g, T, alpha,
-    radius, height in scale heights); exactly `events` collisions per cell."""
+               events: int = 1000, philox_seed: int = 0, V: float = 1e36,
+               counts=None) -> dict:
+    """Independent cells with log-uniform particle counts in [n_lo, n_hi]
+    (or the given counts), log-uniform masses 1e-12 .. 1e2 g, random local
+    gas (rho_g, T, alpha, radius, height in scale heights); exactly `events`
+    collisions per cell."""
     rng = np.random.default_rng(seed)
-    counts = np.rint(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), n_cells))).astype(np.int32)
+    if counts is None:
+        counts = np.rint(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), n_cells))).astype(np.int32)
+    else:
+        counts = np.asarray(counts, dtype=np.int32)
+        n_cells = len(counts)
     cell_start, order = _explicit_cells(counts)
     N = int(cell_start[-1])
     params = benchmark_params(seed=philox_seed, flags=list(VELOCITY_SOURCES) + ["coag"])
@@ -161,7 +167,7 @@ def c4_batched(seed: int = 0, n_cells: int = 4096, n_lo: int = 64, n_hi: int = 1
     r_c = AU * 10.0 ** rng.uniform(0.0, 2.0, n_cells)
     zeta = rng.uniform(0.0, 2.0, n_cells)
     gas = np.stack([np.full(n_cells, V), rho_g, T, alpha, r_c, zeta], axis=1)
-    Mc = 0.01 * rho_g * V / counts
+    Mc = 0.01 * rho_g * V / np.maximum(counts, 1)
     part["M"][:] = np.repeat(Mc, counts)
     return dict(name="c4_batched", params=params, particles=part,
                 cells=dict(cell_start=cell_start, order=order, gas=gas),

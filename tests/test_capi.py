@@ -1,0 +1,101 @@
+"""The C-ABI library without a GPU: it loads, exports every function that
+include/mcd.h declares, its ctypes mirrors have the header's layout, and
+argument validation rejects bad input before any device call."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2507_21239_amd import _lib
+from paper_2507_21239_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mcd.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mcd_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = _lib.load()
+    declared = _declared_functions()
+    assert set(declared) == set(_lib.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (mcd_[a-z_]+)\b", out))
+    assert set(declared) <= exported
+
+
+def test_struct_layouts_match_header(tmp_path):
+    src = tmp_path / "layout.c"
+    structs = {"mcd_params": _lib.Params, "mcd_particles": _lib.Particles,
+               "mcd_cells": _lib.Cells, "mcd_stats": _lib.Stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mcd.h"', "int main(void){"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0;}")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        s, f, v = line.split()
+        got[(s, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def _init(params, n=10):
+    lib = _lib.load()
+    p = _lib.make_params(params)
+    fake = 0x1000   # never dereferenced: validation fails first
+    parts = _lib.Particles(n, fake, fake, fake, fake, fake, None)
+    ctx = C.c_void_p()
+    return lib.mcd_init(C.byref(p), C.byref(parts), None, C.byref(ctx)), ctx
+
+
+@pytest.mark.parametrize("bad", [
+    dict(T0=float("nan")), dict(sigma_g0=-1.0), dict(v_frag=0.0), dict(dm_max=1.5),
+    dict(erosion_ratio=0.5), dict(kernel=7), dict(n_r=0), dict(n_comp=9), dict(flags=1 << 20),
+    dict(alpha=-1e-3), dict(column=1, r_col=0.0),
+])
+def test_init_rejects_bad_params(bad):
+    st, ctx = _init(W.benchmark_params(**bad))
+    assert st == _lib.MCD_EINVAL
+    assert not ctx.value
+
+
+def test_init_rejects_bad_particles():
+    lib = _lib.load()
+    p = _lib.make_params(W.benchmark_params())
+    ctx = C.c_void_p()
+    parts = _lib.Particles(0, 1, 1, 1, 1, 1, None)
+    assert lib.mcd_init(C.byref(p), C.byref(parts), None, C.byref(ctx)) == _lib.MCD_EINVAL
+    parts = _lib.Particles(10, 1, None, 1, 1, 1, None)
+    assert lib.mcd_init(C.byref(p), C.byref(parts), None, C.byref(ctx)) == _lib.MCD_EINVAL
+    p = _lib.make_params(W.benchmark_params(n_comp=8))
+    parts = _lib.Particles(10, 1, 1, 1, 1, 1, None)
+    assert lib.mcd_init(C.byref(p), C.byref(parts), None, C.byref(ctx)) == _lib.MCD_EINVAL
+    assert lib.mcd_init(None, C.byref(parts), None, C.byref(ctx)) == _lib.MCD_EINVAL
+
+
+def test_null_context_calls_are_rejected():
+    lib = _lib.load()
+    assert lib.mcd_bin(None, None) == _lib.MCD_EINVAL
+    assert lib.mcd_step(None, 1.0, 0, 1) == _lib.MCD_EINVAL
+    assert lib.mcd_rates(None, 0, None, 0, None) == _lib.MCD_EINVAL
+    assert lib.mcd_get_stats(None, None) == _lib.MCD_EINVAL
+    assert lib.mcd_last_error(None) == b"null context"
+    assert lib.mcd_philox(None, 0, 0, None, -1, None) == _lib.MCD_EINVAL
+    lib.mcd_free(None)

@@ -1,0 +1,271 @@
+"""GPU parity of the HIP collision step against the CPU oracle, through the
+C ABI, on identical seeded inputs.
+
+Bars: integer and index results (Philox words, binning, event sequences)
+bit-exact; FP64 floating point within 1e-12 relative (the two sides use
+different cbrt / pow / exp / log libraries and different summation orders,
+each good to a few ulps; the pair rate is a short product of such values);
+FP32 rates within 1e-4 relative (single-precision pair arithmetic with the
+hardware reciprocal and square root, about 1e-6, plus FP32 accumulation of up
+to 2048 terms)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2507_21239_amd import workloads as W
+
+from gpu_common import (compare_logs, edge_size_work, run_gpu_explicit, run_oracle_explicit, say)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _api():
+    from paper_2507_21239_amd import api
+    return api
+
+
+def test_philox_words_bit_exact():
+    api = _api()
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2 ** 32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[0] = 0
+    ctr[1] = 0xFFFFFFFF
+    key = 0x299F31D0A4093822
+    say("philox", ctr.shape)
+    out = api.philox(torch.from_numpy(ctr.view(np.int32)).cuda(), key).cpu().numpy().view(np.uint32)
+    for k in range(0, 4096, 37):
+        assert np.array_equal(out[k], O.philox(ctr[k], [key & 0xFFFFFFFF, key >> 32]))
+
+
+@pytest.mark.parametrize("N,n_r,n_z,seed", [(5000, 10, 5, 0), (4000, 1, 20, 1), (2049, 7, 3, 2),
+                                            (100_000, 50, 10, 3), (33, 4, 8, 4)])
+def test_binning_bit_exact(N, n_r, n_z, seed):
+    api = _api()
+    rng = np.random.default_rng(seed)
+    p = W.benchmark_params(n_r=n_r, n_z=n_z)
+    r = W.AU * 10.0 ** rng.uniform(0, 2, N)
+    z = np.abs(rng.standard_normal(N)) * 0.05 * r
+    k = rng.choice(N, N // 5, replace=False)
+    r[k[: len(k) // 2]] = r[k[len(k) // 2: 2 * (len(k) // 2)]]
+    z[k[::3]] = z[k[0]]
+    z[k[1::7]] = 0.0
+    active = (rng.random(N) > 0.1).astype(np.uint8)
+    part = dict(r=r, z=z, m=np.full(N, 1e-11), M=np.ones(N), active=active)
+    say("binning", N, n_r, n_z)
+    sim = api.Simulation(p, api.to_device(part), precision="fp64")
+    sim.bin()
+    cells = {k_: v.cpu().numpy() for k_, v in sim.cells().items()}
+    ref = O.bin_particles(p, r, z, active)
+    assert np.array_equal(cells["cell_start"], ref["cell_start"])
+    assert np.array_equal(cells["order"], ref["order"])
+    assert np.array_equal(cells["geom"], ref["geom"])
+    occ = np.diff(ref["cell_start"]) > 0
+    g, gr = cells["gas"][occ], ref["gas"][occ]
+    assert np.all(np.abs(g - gr) <= 1e-13 * np.abs(gr) + 1e-300)
+    assert np.all(cells["gas"][~occ] == 0.0)
+    assert sim.stats()["n_active"] == active.sum()
+    sim.close()
+
+
+def _rates_check(precision, tol):
+    api = _api()
+    work = edge_size_work()
+    dev = api.to_device(work["particles"])
+    sim = api.Simulation(work["params"], dev, precision=precision)
+    sim.bin(api.cells_to_device(work["cells"]))
+    cs = work["cells"]["cell_start"]
+    worst = 0.0
+    for c in range(len(cs) - 1):
+        n = int(cs[c + 1] - cs[c])
+        if n == 0:
+            continue
+        say("rates", precision, "cell", c, "n", n)
+        Rg, rsg = sim.rates(c, n)
+        Rg, rsg = Rg.cpu().numpy(), rsg.cpu().numpy()
+        members = work["cells"]["order"][cs[c]:cs[c + 1]]
+        Ro, rso = O.cell_rates(work["params"], work["cells"]["gas"][c], members,
+                               work["particles"]["m"], work["particles"]["M"])
+        assert np.all(Ro > 0)
+        err = np.max(np.abs(Rg - Ro) / Ro)
+        err_rs = np.max(np.abs(rsg - rso) / rso)
+        worst = max(worst, err, err_rs)
+        assert err <= tol and err_rs <= tol, (c, n, err, err_rs)
+    sim.close()
+    return worst
+
+
+def test_rates_fp64_match_oracle():
+    worst = _rates_check("fp64", 1e-12)
+    say("fp64 rate max rel err", worst)
+
+
+def test_rates_mixed_within_fp32_tolerance():
+    worst = _rates_check("mixed", 1e-4)
+    say("mixed rate max rel err", worst)
+
+
+@pytest.mark.parametrize("schedule", ["plain", "batched"])
+def test_event_sequence_fp64_bit_exact(schedule):
+    work = edge_size_work(events=200)
+    opart, oout = run_oracle_explicit(work, log_per_cell=220, threads=8)
+    gpart, gstats, glog = run_gpu_explicit(work, "fp64", schedule, log_per_cell=220)
+    assert compare_logs(oout["log"], oout["stats"], glog) == []
+    assert gstats["events"] == int(oout["stats"]["events"].sum())
+    assert gstats["outcomes"] == [int(x) for x in oout["stats"]["outcomes"].sum(axis=0)]
+    assert np.array_equal(gpart["M"], work["particles"]["M"])
+    rel = np.abs(gpart["m"] - opart["m"]) / opart["m"]
+    assert rel.max() <= 1e-12, rel.max()
+    assert gstats["device_flags"] == 0
+
+
+def test_constant_kernel_exact_on_gpu():
+    for seed in range(4):
+        work = W.c1_single_cell(seed=seed)
+        opart, oout = run_oracle_explicit(work, log_per_cell=4000)
+        gpart, gstats, glog = run_gpu_explicit(work, "fp64", "batched", log_per_cell=4000)
+        assert compare_logs(oout["log"], oout["stats"], glog) == []
+        assert np.array_equal(gpart["m"], opart["m"])      # integer masses, exact
+
+
+def test_time_limited_cells_fp64():
+    work = W.c4_batched(seed=11, n_cells=24, n_lo=16, n_hi=400, events=0)
+    work["dt"] = 1.0e8      # seconds: a few to ~1000 events per cell
+    work["max_events"] = 0
+    opart, oout = run_oracle_explicit(work, log_per_cell=4096, threads=8)
+    assert oout["stats"]["events"].sum() > 1000
+    gpart, gstats, glog = run_gpu_explicit(work, "fp64", "batched", log_per_cell=4096)
+    assert compare_logs(oout["log"], oout["stats"], glog) == []
+    rel = np.abs(gpart["m"] - opart["m"]) / opart["m"]
+    assert rel.max() <= 1e-12
+
+
+def test_transport_step_matches_oracle():
+    api = _api()
+    work = W.c3_disk(seed=5, N=20000, n_r=20, n_z=10)
+    p = dict(work["params"])
+    p["flags"] = [f for f in p["flags"] if f != "coag"]
+    part = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in work["particles"].items()}
+    part["m"] = 10.0 ** np.random.default_rng(1).uniform(-12, 1, len(part["m"]))
+    part["r"][:50] = W.AU * 1.0000001    # some particles leave through the inner edge
+    dev = api.to_device(part)
+    say("transport", len(part["m"]))
+    sim = api.Simulation(p, dev, precision="fp64")
+    sim.bin()
+    sim.step(work["dt"] * 20, 0, 1)
+    torch.cuda.synchronize()
+    ref = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in part.items()}
+    O.transport(p, ref, 0, work["dt"] * 20)
+    assert np.array_equal(dev["active"].cpu().numpy(), ref["active"])
+    assert ref["active"].sum() < len(part["m"])
+    for k in ("r", "z"):
+        g = dev[k].cpu().numpy()
+        assert np.all(np.abs(g - ref[k]) <= 1e-12 * np.abs(ref[k]) + 1e-300), k
+    sim.close()
+
+
+@pytest.mark.parametrize("schedule", ["plain", "batched"])
+def test_full_disk_steps_fp64(schedule):
+    """bin -> collide -> transport, three steps of a small disk, with the
+    composition fractions; the batched schedule replays a HIP graph."""
+    api = _api()
+    work = W.c3_disk(seed=7, N=20000, n_r=20, n_z=10, n_comp=8)
+    p = dict(work["params"])
+    dt = 30.0 * W.YR
+    ref = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in work["particles"].items()}
+    dev = api.to_device(work["particles"])
+    say("disk steps", schedule)
+    sim = api.Simulation(p, dev, precision="fp64", schedule=schedule)
+    sim.bin()
+    sim.step(dt, 0, 3)
+    st = sim.stats()
+    ev = 0
+    for s in range(3):
+        out = O.step(p, ref, s, dt, 0, threads=8)
+        ev += int(out["stats"]["events"].sum())
+    assert st["events"] == ev and ev > 0
+    assert st["steps"] == 3
+    g = {k: v.cpu().numpy() for k, v in dev.items()}
+    assert np.array_equal(g["active"], ref["active"])
+    for k in ("m", "r", "z"):
+        assert np.all(np.abs(g[k] - ref[k]) <= 1e-11 * np.abs(ref[k]) + 1e-300), k
+    assert np.max(np.abs(g["comp"] - ref["comp"])) <= 1e-6
+    assert np.allclose(g["comp"].sum(axis=0), 1.0, atol=1e-5)
+    sim.close()
+
+
+def test_graph_replay_matches_eager_steps():
+    api = _api()
+    work = W.c3_disk(seed=9, N=8000, n_r=8, n_z=10)
+    dt = 30.0 * W.YR
+    res = []
+    for mode in ("graph", "eager"):
+        dev = api.to_device(work["particles"])
+        sim = api.Simulation(work["params"], dev, precision="fp64", schedule="batched")
+        sim.bin()
+        say("graph replay", mode)
+        if mode == "graph":
+            sim.step(dt, 0, 4)
+        else:
+            for _ in range(4):
+                sim.step(dt, 0, 1)
+        res.append(({k: v.cpu().numpy() for k, v in dev.items()}, sim.stats()))
+        sim.close()
+    (a, sa), (b, sb) = res
+    assert sa["events"] == sb["events"] and sa["steps"] == sb["steps"] == 4
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_full_size_c4_sampled_cells_fp64():
+    """The benchmark's batched workload at full size (4096 cells, 64..1024
+    particles, 1000 events): sampled cells replayed on the oracle."""
+    work = W.c4_batched(seed=0)
+    gpart, gstats, glog = run_gpu_explicit(work, "fp64", "batched", log_per_cell=1000)
+    assert gstats["events"] == 4096 * 1000
+    cs = work["cells"]["cell_start"]
+    sizes = np.diff(cs)
+    pick = sorted(set([int(np.argmax(sizes)), int(np.argmin(sizes))] +
+                      list(np.random.default_rng(1).choice(len(sizes), 4, replace=False))))
+    for c in pick:
+        sub = W.subset_cells(work, np.array([c]))
+        say("oracle cell", c, "n", int(sizes[c]))
+        # the cell index is part of the Philox counter: run the oracle cell with its own index
+        part = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in sub["particles"].items()}
+        log = np.zeros(1000, dtype=O.EVENT_DTYPE)
+        st = np.zeros(1, dtype=O.STATS_DTYPE)
+        import ctypes as C
+        O.lib().orc_collide_cell(C.byref(O.make_params(sub["params"])),
+                                 O._ptr(np.ascontiguousarray(sub["cells"]["gas"][0]), C.c_double),
+                                 c, 0, int(sizes[c]),
+                                 O._ptr(np.ascontiguousarray(sub["cells"]["order"]), C.c_int32),
+                                 O._ptr(part["m"], C.c_double), O._ptr(part["M"], C.c_double),
+                                 None, len(part["m"]), 0.0, 1000, log.ctypes.data, 1000,
+                                 st.ctypes.data)
+        g = glog[c, :, :3]
+        o = np.stack([log["i"], log["j"], log["outcome"]], axis=1)
+        assert np.array_equal(g, o), c
+        rel = np.abs(gpart["m"][cs[c]:cs[c + 1]] - part["m"]) / part["m"]
+        assert rel.max() <= 1e-12
+
+
+def test_errors_and_state():
+    api = _api()
+    work = edge_size_work(events=5)
+    dev = api.to_device(work["particles"])
+    sim = api.Simulation(work["params"], dev, precision="fp64")
+    with pytest.raises(api.MCDError) as e:
+        sim.step(1.0, 0, 1)
+    assert e.value.status == -4          # MCD_ESTATE: no grid yet
+    bad = api.cells_to_device(work["cells"])
+    bad["order"][3] = len(work["particles"]["m"]) + 5
+    with pytest.raises(api.MCDError) as e:
+        sim.bin(bad)
+    assert e.value.status == -1
+    sim.bin(api.cells_to_device(work["cells"]))
+    with pytest.raises(api.MCDError):
+        sim.step(0.0, 0, 1)              # no limit set
+    with pytest.raises(api.MCDError):
+        sim.rates(999, 1)
+    sim.close()
