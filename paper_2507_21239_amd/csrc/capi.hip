@@ -43,7 +43,7 @@ namespace {
 
 constexpr int kSmallMax = 256;        // cells up to this size run on one wave
 constexpr int kBigMax = 2048;         // largest cell of the batched schedule
-constexpr int kPlainMax = 1024;       // largest cell of the plain schedule
+constexpr int kPlainMax = 2048;       // largest cell of the plain schedule
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
 constexpr uint32_t kKnownFlags = DV_BROWNIAN | DV_TURB | DV_RADIAL | DV_AZIMUTHAL | DV_SETTLING |
                                  TR_DRIFT | TR_SETTLE | TR_MIX_R | TR_MIX_Z | COAG;
@@ -206,15 +206,14 @@ mcd_status plan_lists(mcd_ctx *c, const std::vector<int32_t> &sizes) {
   c->big_cap = mb > 0 ? (mb + 255) / 256 * 256 : 0;
   c->small_cap = std::max(64, (ms + 63) / 64 * 64);
   c->max_cell = std::max(mb, ms);
-  if (c->prm.schedule == MCD_SCHED_PLAIN) c->small_cap = std::max(64, (c->max_cell + 63) / 64 * 64);
-  const size_t lds = c->prm.precision == MCD_FP64 ? region_bytes<double>(c->big_cap, 4)
-                                                   : region_bytes<float>(c->big_cap, 4);
-  const size_t lds_small = c->prm.precision == MCD_FP64
-                               ? region_bytes<double>(c->small_cap, 1) *
-                                     (c->prm.schedule == MCD_SCHED_PLAIN ? 1 : 4)
-                               : region_bytes<float>(c->small_cap, 1) *
-                                     (c->prm.schedule == MCD_SCHED_PLAIN ? 1 : 4);
-  if (std::max(lds, lds_small) > kLdsBytes)
+  // the plain schedule runs every cell on one four-wave workgroup
+  if (c->prm.schedule == MCD_SCHED_PLAIN) c->big_cap = std::max(256, (c->max_cell + 255) / 256 * 256);
+  const bool f64 = c->prm.precision == MCD_FP64;
+  const size_t lds_big = f64 ? region_bytes<double>(c->big_cap, 4) : region_bytes<float>(c->big_cap, 4);
+  const size_t lds_small = 4 * (f64 ? region_bytes<double>(c->small_cap, 1)
+                                    : region_bytes<float>(c->small_cap, 1));
+  const size_t lds = c->prm.schedule == MCD_SCHED_PLAIN ? lds_big : std::max(lds_big, lds_small);
+  if (lds > kLdsBytes)
     return fail(c, MCD_EINVAL, "largest cell does not fit the 160 KB LDS in this precision");
   if (!big.empty())
     MCD_HIP(c, hipMemcpy(c->d_big, big.data(), big.size() * sizeof(int32_t), hipMemcpyHostToDevice));

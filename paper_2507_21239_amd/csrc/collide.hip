@@ -6,170 +6,294 @@
 // outcome (sticking / erosion / fragmentation) to i only, update every row
 // sum incrementally for the changed particle and recompute row i.
 //
-// A cell is processed by a team of T waves (T = 1 or 4).  The cell's n
-// particles are laid out in canonical order j = 0..n-1; team lane t owns the
-// contiguous slots j = t*K .. t*K + K - 1 (K = ceil(n / 64T)), so the
-// cumulative rate of j is the team prefix of the lanes' partial sums plus a
-// short in-lane prefix.  Particle records live in LDS as structure-of-arrays
-// indexed by s = q*64T + t (slot q of lane t): lanes of a wave touch
-// consecutive words.  Row sums (FP64), the per-event row values and the
-// column values stay in registers of the owning lane.
+// A cell is processed by a team of nw waves (1, or 4 for cells above 256
+// particles).  The cell's n particles are in canonical order j = 0..n-1; team
+// lane t owns the contiguous slots j = t*K .. t*K+K-1 (K = ceil(n/(64 nw))),
+// so the cumulative rate of j is the team prefix of the lanes' partial sums
+// plus a short in-lane prefix.  Prefix sums are FP64 DPP scans; four-wave
+// teams exchange wave totals through LDS (two barriers per selection, one
+// for the new row sum).  Particle records live in LDS as packed vectors
+// indexed by s = q*64nw + t (slot q of lane t), so a wave reads consecutive
+// 16-byte words.  Row sums (FP64), the per-event row values, masses and
+// particle indices stay in registers of the owning lane; masses go back to
+// HBM once, when the cell is done.
 #include "device_common.hpp"
 #include "internal.hpp"
 
 namespace mcd {
 
+// ---------------------------------------------------------------------------
+// packed LDS records
+// ---------------------------------------------------------------------------
 template <typename RT>
-struct Region {
-  RT *f;          // 10 arrays of cap: m, im, a, St, h, q1, vr, vp, vz, nd
-  double *m64;    // exact masses
-  double *M64;    // swarm masses
-  int32_t *idx;   // global particle index
-  void *scratch;  // team reduction scratch
-  int cap;
+struct RecStore;
 
-  __device__ Region(char *base, int cap_) : cap(cap_) {
-    f = (RT *)base;
-    m64 = (double *)(base + (size_t)10 * cap * sizeof(RT));
-    M64 = m64 + cap;
-    idx = (int32_t *)(M64 + cap);
-    scratch = (void *)(idx + cap);
-  }
-  __device__ Rec<RT> load(int s) const {
-    Rec<RT> r;
-    r.m = f[s];
-    r.im = f[cap + s];
-    r.a = f[2 * cap + s];
-    r.St = f[3 * cap + s];
-    r.h = f[4 * cap + s];
-    r.q1 = f[5 * cap + s];
-    r.vr = f[6 * cap + s];
-    r.vp = f[7 * cap + s];
-    r.vz = f[8 * cap + s];
-    r.nd = f[9 * cap + s];
+template <>
+struct RecStore<float> {
+  float4 *A;  // im, a, St, h
+  float4 *B;  // q1, vr, vp, vz
+  float2 *C;  // nd, m
+  __device__ RecStore(char *base, int cap)
+      : A((float4 *)base), B((float4 *)base + cap), C((float2 *)((float4 *)base + 2 * cap)) {}
+  __device__ Rec<float> load(int s) const {
+    const float4 a = A[s], b = B[s];
+    const float2 c = C[s];
+    Rec<float> r;
+    r.im = a.x; r.a = a.y; r.St = a.z; r.h = a.w;
+    r.q1 = b.x; r.vr = b.y; r.vp = b.z; r.vz = b.w;
+    r.nd = c.x; r.m = c.y;
     return r;
   }
-  __device__ void store(int s, const Rec<RT> &r) {
-    f[s] = r.m;
-    f[cap + s] = r.im;
-    f[2 * cap + s] = r.a;
-    f[3 * cap + s] = r.St;
-    f[4 * cap + s] = r.h;
-    f[5 * cap + s] = r.q1;
-    f[6 * cap + s] = r.vr;
-    f[7 * cap + s] = r.vp;
-    f[8 * cap + s] = r.vz;
-    f[9 * cap + s] = r.nd;
+  __device__ void store(int s, const Rec<float> &r) const {
+    A[s] = make_float4(r.im, r.a, r.St, r.h);
+    B[s] = make_float4(r.q1, r.vr, r.vp, r.vz);
+    C[s] = make_float2(r.nd, r.m);
   }
 };
 
-// Choose the first slot whose cumulative value exceeds target.  v[] are the
-// caller lane's K values (in canonical order), part their sum, incl / excl
-// the team's inclusive / exclusive prefix of part.  If rounding leaves no
+template <>
+struct RecStore<double> {
+  double2 *D;  // 5 arrays: (im, a) (St, h) (q1, vr) (vp, vz) (nd, m)
+  int cap;
+  __device__ RecStore(char *base, int cap_) : D((double2 *)base), cap(cap_) {}
+  __device__ Rec<double> load(int s) const {
+    const double2 a = D[s], b = D[cap + s], c = D[2 * cap + s], d = D[3 * cap + s],
+                  e = D[4 * cap + s];
+    Rec<double> r;
+    r.im = a.x; r.a = a.y; r.St = b.x; r.h = b.y; r.q1 = c.x; r.vr = c.y;
+    r.vp = d.x; r.vz = d.y; r.nd = e.x; r.m = e.y;
+    return r;
+  }
+  __device__ void store(int s, const Rec<double> &r) const {
+    D[s] = make_double2(r.im, r.a);
+    D[cap + s] = make_double2(r.St, r.h);
+    D[2 * cap + s] = make_double2(r.q1, r.vr);
+    D[3 * cap + s] = make_double2(r.vp, r.vz);
+    D[4 * cap + s] = make_double2(r.nd, r.m);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// team: nw waves of one workgroup, runtime size
+// ---------------------------------------------------------------------------
+struct Team {
+  int nw, wave, lane, tl;
+  TeamScratch *S;
+  int phase;
+  __device__ void sync() const {
+    if (nw > 1)
+      block_lds_sync();
+    else
+      wave_lds_sync();
+  }
+  // team-inclusive prefix of x over team lanes; total on every lane
+  __device__ double scan(double x, double &total) {
+    const double inc = wave_incl_scan(x);
+    const double wt = readlane_d(inc, 63);
+    if (nw == 1) {
+      total = wt;
+      return inc;
+    }
+    phase ^= 1;
+    if (lane == 63) S->tot[phase][wave] = wt;
+    block_lds_sync();
+    double off = 0.0, tot = 0.0;
+    for (int w = 0; w < nw; ++w) {
+      const double v = S->tot[phase][w];
+      if (w < wave) off += v;
+      tot += v;
+    }
+    total = tot;
+    return off + inc;
+  }
+  // team-inclusive prefix of a plus the totals of a and b (one exchange)
+  __device__ double scan2(double a, double b, double &tot_a, double &tot_b) {
+    const double ia = wave_incl_scan(a);
+    const double ib = wave_incl_scan(b);
+    const double wa = readlane_d(ia, 63), wb = readlane_d(ib, 63);
+    if (nw == 1) {
+      tot_a = wa;
+      tot_b = wb;
+      return ia;
+    }
+    phase ^= 1;
+    if (lane == 63) {
+      S->tot[phase][wave] = wa;
+      S->tot[phase][4 + wave] = wb;
+    }
+    block_lds_sync();
+    double off = 0.0, ta = 0.0, tb = 0.0;
+    for (int w = 0; w < nw; ++w) {
+      const double v = S->tot[phase][w];
+      if (w < wave) off += v;
+      ta += v;
+      tb += S->tot[phase][4 + w];
+    }
+    tot_a = ta;
+    tot_b = tb;
+    return off + ia;
+  }
+};
+
+// particle state after a collision: FP64 formulas for the FP64 path, the
+// FP32 formulas with per-cell FP32 factors for the mixed path
+template <typename RT>
+struct RecAfter;
+template <>
+struct RecAfter<double> {
+  __device__ static Rec<double> get(const Model &P, const TeamScratch *S, double m, double M) {
+    return make_rec<double>(P, S->gas, m, M, 1.0);
+  }
+};
+template <>
+struct RecAfter<float> {
+  __device__ static Rec<float> get(const Model &, const TeamScratch *S, double m, double M) {
+    return make_rec_f(S->cf, m, M);
+  }
+};
+
+// Pick the first slot whose cumulative value exceeds target.  v[] are the
+// lane's K values in canonical order, part their sum, incl the team-inclusive
+// prefix of part.  A lane with an empty partial is never chosen (the team
+// prefix is not exactly monotone under rounding); if rounding leaves no
 // prefix above the target, the last nonzero entry is taken.  Returns the
-// chosen slot q (uniform) and sets owner (team lane) and the owner's payload
-// value pay[q] (uniform).
-template <int KMAX, int T, typename PT>
-__device__ inline int team_select(Team<T> &tm, double incl, double excl, double part,
-                                  const double *v, const PT *pay, int K, double target,
-                                  int &owner, double &payload) {
-  int fb;
-  // a lane with an empty partial is never chosen (the team prefix is not
-  // exactly monotone under rounding)
-  const int first = tm.first_lane(incl > target && part > 0.0, part > 0.0, &fb);
-  const int src = first >= 0 ? first : fb;
-  int qsel = -1;
-  double pv = 0.0;
-  if (tm.tl == src) {
-    double cum = excl;
+// chosen slot, its owner and the owner's payloads a0[q], a1[q], a2[q], ai[q]
+// on every lane of the team.
+template <int KMAX, typename VT, typename P2>
+__device__ inline Cand team_pick(Team &tm, double incl, double part, const VT *v, int K,
+                                 double target, const double *a0, const double *a1,
+                                 const P2 *a2, const int *ai) {
+  const bool hit = incl > target && part > 0.0;
+  const uint64_t bh = ballot(hit), bf = ballot(part > 0.0);
+  const int first = first_set(bh);
+  const int src = first >= 0 ? first : last_set(bf);
+  Cand c{0.0, 0.0, 0.0, -1, -1, first >= 0 ? 1 : 0, -1};
+  if (tm.lane == src) {
+    double cum = incl - part;
     int last = -1;
     bool found = false;
+    int qsel = -1;
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) {
       if (q < K && !found) {
-        if (v[q] > 0.0) {
-          last = q;
-          pv = (double)pay[q];
-        }
-        cum += v[q];
+        if (v[q] > (VT)0) last = q;
+        cum += (double)v[q];
         if (first >= 0 && cum > target) {
           qsel = q;
-          pv = (double)pay[q];
           found = true;
         }
       }
     }
-    if (!found) {
-      qsel = last;
+    if (!found) qsel = last;
 #pragma unroll
-      for (int q = 0; q < KMAX; ++q)
-        if (q == last) pv = (double)pay[q];
+    for (int q = 0; q < KMAX; ++q) {
+      if (q == qsel) {
+        c.p0 = a0[q];
+        c.p1 = a1[q];
+        c.p2 = (double)a2[q];
+        c.gi = ai[q];
+      }
     }
+    c.q = qsel;
+    c.lane = tm.tl;
   }
-  tm.bcast(src < 0 ? 0 : src, qsel, pv);
-  owner = src;
-  payload = pv;
-  return qsel;
+  if (tm.nw == 1) {
+    Cand o{0.0, 0.0, 0.0, -1, -1, 0, -1};
+    if (src < 0) return o;
+    o.q = readlane_i(c.q, src);
+    o.lane = src;
+    o.hit = first >= 0 ? 1 : 0;
+    o.gi = readlane_i(c.gi, src);
+    o.p0 = readlane_d(c.p0, src);
+    o.p1 = readlane_d(c.p1, src);
+    o.p2 = readlane_d(c.p2, src);
+    return o;
+  }
+  tm.phase ^= 1;
+  Cand *slot = &tm.S->cand[tm.phase][tm.wave];
+  if (tm.lane == 0 && src < 0) slot->q = -1;
+  if (tm.lane == src) *slot = c;
+  block_lds_sync();
+  int wsel = -1;
+  for (int w = tm.nw - 1; w >= 0; --w) {
+    const Cand &x = tm.S->cand[tm.phase][w];
+    if (x.q >= 0 && x.hit) wsel = w;
+  }
+  if (wsel < 0) {
+    for (int w = 0; w < tm.nw; ++w)
+      if (tm.S->cand[tm.phase][w].q >= 0) wsel = w;
+  }
+  if (wsel < 0) {
+    Cand o{0.0, 0.0, 0.0, -1, -1, 0, -1};
+    return o;
+  }
+  return tm.S->cand[tm.phase][wsel];
 }
 
-template <typename RT, int KMAX, int T>
-__device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap, int wave,
+template <typename RT, int KMAX>
+__device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap, int nw, int wave,
                              int lane, uint32_t step) {
   const int s0 = A.cell_start[cell];
   const int n = A.cell_start[cell + 1] - s0;
   if (n <= 0) return;
-  constexpr int TL = 64 * T;
+  const int TL = 64 * nw;
   const int K = (n + TL - 1) / TL;
-  Region<RT> R(base, cap);
-  Team<T> tm(wave, lane, R.scratch);
+  const RecStore<RT> R(base, cap);
+  Team tm;
+  tm.nw = nw;
+  tm.wave = wave;
+  tm.lane = lane;
+  tm.tl = wave * 64 + lane;
+  tm.S = (TeamScratch *)(base + (size_t)cap * rec_bytes<RT>());
+  tm.phase = 0;
   const int tl = tm.tl;
   if (K > KMAX || K * TL > cap) {
     if (tl == 0) atomicOr(&A.state->flags, FLAG_CAPACITY);
     return;
   }
-
   Gas g;
   gas_from_primaries(A.P, A.gas + (size_t)cell * 6, g);
-  const PairConst<RT> pc = make_pair_const<RT>(A.P, g);
   if (!(g.V > 0.0)) {
     if (tl == 0) atomicOr(&A.state->flags, FLAG_BAD_VOLUME);
     return;
   }
+  const PairConst<RT> pc = make_pair_const<RT>(A.P, g);
 
-  // ---- load members, choose the cell's rate scale, build records --------
-  double m64[KMAX], M64[KMAX];
-  int idx[KMAX];
+  // ---- members: masses and indices stay in the owning lane's registers ---
+  double m64[KMAX];
+  int gix[KMAX];
   double ndmax = 0.0;
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) {
     const int j = tl * K + q;
-    idx[q] = -1;
+    gix[q] = -1;
     m64[q] = 1.0;
-    M64[q] = 0.0;
     if (q < K && j < n) {
-      idx[q] = A.order[s0 + j];
-      m64[q] = A.m[idx[q]];
-      M64[q] = A.M[idx[q]];
-      ndmax = fmax(ndmax, M64[q] / (m64[q] * g.V));
+      gix[q] = A.order[s0 + j];
+      m64[q] = A.m[gix[q]];
+      ndmax = fmax(ndmax, A.M[gix[q]] / (m64[q] * g.V));
     }
   }
-  double scale = 1.0;  // rates are carried as r * scale (FP32 range)
+  double scale = 1.0;  // FP32 rates are carried as r * scale, a power of two
   if (sizeof(RT) == 4) {
-    ndmax = tm.max(ndmax);
+    ndmax = wave_max_nonneg(ndmax);
+    if (nw > 1) {
+      if (lane == 0) tm.S->tot[0][wave] = ndmax;
+      block_lds_sync();
+      for (int w = 0; w < nw; ++w) ndmax = fmax(ndmax, tm.S->tot[0][w]);
+      block_lds_sync();
+    }
     int e2 = 0;
     frexp(ndmax, &e2);
     scale = ldexp(1.0, -e2);
   }
+  if (tl == 0) {
+    tm.S->gas = g;
+    tm.S->cf = make_cellf(A.P, g, scale);
+  }
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) {
-    const int j = tl * K + q;
-    if (q < K && j < n) {
-      const int s = q * TL + tl;
-      R.store(s, make_rec<RT>(A.P, g, m64[q], M64[q], scale));
-      R.m64[s] = m64[q];
-      R.M64[s] = M64[q];
-      R.idx[s] = idx[q];
-    }
+    if (q < K && tl * K + q < n) R.store(q * TL + tl, make_rec<RT>(A.P, g, m64[q], A.M[gix[q]], scale));
   }
   tm.sync();
 
@@ -177,36 +301,38 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
   double r[KMAX];
   const int lanes_used = (n + K - 1) / K;
 #pragma unroll
-  for (int q = 0; q < KMAX; ++q) {
-    r[q] = 0.0;
-    if (q < K && tl * K + q < n) {
-      const Rec<RT> mine = R.load(q * TL + tl);
-      RT acc = (RT)0;
-      for (int t2 = 0; t2 < lanes_used; ++t2) {
-        for (int q2 = 0; q2 < K; ++q2) {
-          if (t2 * K + q2 >= n) break;
-          const Rec<RT> rk = R.load(q2 * TL + t2);
-          RT dv;
-          const RT Kx = pair_kernel(pc, mine, rk, dv);
-          acc += swarm_rate(pc, mine, rk, Kx);
-        }
+  for (int q = 0; q < KMAX; ++q) r[q] = 0.0;
+#pragma unroll 1
+  for (int q = 0; q < K; ++q) {
+    if (tl * K + q >= n) break;
+    const Rec<RT> mine = R.load(q * TL + tl);
+    RT acc = (RT)0;
+    for (int t2 = 0; t2 < lanes_used; ++t2) {
+      for (int q2 = 0; q2 < K; ++q2) {
+        if (t2 * K + q2 >= n) break;
+        const Rec<RT> rk = R.load(q2 * TL + t2);
+        RT dv;
+        const RT Kx = pair_kernel(pc, mine, rk, dv);
+        acc += swarm_rate(pc, mine, rk, Kx);
       }
-      r[q] = (double)acc;
     }
+#pragma unroll
+    for (int qq = 0; qq < KMAX; ++qq)
+      if (qq == q) r[qq] = (double)acc;
   }
 
   // ---- events ------------------------------------------------------------
   double t = 0.0;
   int64_t e = 0;
-  unsigned long long oc_count[4] = {0ull, 0ull, 0ull, 0ull};
+  uint32_t oc_count[4] = {0u, 0u, 0u, 0u};
   const uint32_t c32 = (uint32_t)cell;
-  for (;;) {
-    double part = 0.0;
+  const bool timed = A.dt > 0.0;
+  double part = 0.0, Rtot;
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q)
-      if (q < K) part += r[q];
-    double excl, Rtot;
-    const double incl = tm.incl_scan(part, excl, Rtot);
+  for (int q = 0; q < KMAX; ++q)
+    if (q < K) part += r[q];
+  double incl = tm.scan(part, Rtot);
+  for (;;) {
     if (!(Rtot > 0.0) || !isfinite(Rtot)) {
       if (!isfinite(Rtot) && tl == 0) atomicOr(&A.state->flags, FLAG_BAD_RATE);
       break;
@@ -214,79 +340,80 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     if (A.max_events > 0 && e >= A.max_events) break;
     const U4 w0 = philox4x32_10(U4{(uint32_t)e, c32, step, 0u}, A.P.key0, A.P.key1);
     const U4 w1 = philox4x32_10(U4{(uint32_t)e, c32, step, 1u}, A.P.key0, A.P.key1);
-    const double u1 = u01(w0.x, w0.y), u2 = u01(w0.z, w0.w);
-    const double u3 = u01(w1.x, w1.y), u4 = u01(w1.z, w1.w);
-    const double tau = -log(u1) / Rtot * scale;  // exponential waiting time, true units
-    if (A.dt > 0.0 && t + tau > A.dt) break;   // the next event falls outside the step
-    t += tau;
+    if (timed) {
+      const double tau = -log(u01(w0.x, w0.y)) / Rtot * scale;  // exponential waiting time
+      if (t + tau > A.dt) break;  // the next event falls outside the step
+      t += tau;
+    }
+    const double u2 = u01(w0.z, w0.w), u3 = u01(w1.x, w1.y), u4 = u01(w1.z, w1.w);
 
-    // -- choose i by cumulative row sums
-    int ownI;
-    double dummy;
-    const int qI = team_select<KMAX, T, double>(tm, incl, excl, part, r, r, K, u2 * Rtot, ownI,
-                                               dummy);
-    if (qI < 0 || ownI < 0) {
+    // -- choose i by cumulative row sums (payloads: m_i, index)
+    const Cand ci = team_pick<KMAX, double, double>(tm, incl, part, r, K, u2 * Rtot, m64, r, m64,
+                                                    gix);
+    if (ci.q < 0) {
       if (tl == 0) atomicOr(&A.state->flags, FLAG_BAD_RATE);
       break;
     }
-    const int si = qI * TL + ownI;
+    const int si = ci.q * TL + ci.lane;
+    const int i_local = ci.lane * K + ci.q;
+    const double mi = ci.p0, ri_old = ci.p1;
+    const int gi = ci.gi;
+    const double Mi = A.M[gi];  // needed after the outcome: the load overlaps row i
     const Rec<RT> ri = R.load(si);
-    const double mi = R.m64[si];
-    const double Mi = R.M64[si];
-    const int gi = R.idx[si];
 
     // -- row i before the event: r_ij, r_ji and the relative velocities
-    RT rji[KMAX], dvv[KMAX];
-    double rij[KMAX];
+    RT rij[KMAX], rji[KMAX], dvv[KMAX];
     double part1 = 0.0;
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) {
-      rij[q] = 0.0;
+      rij[q] = (RT)0;
       rji[q] = (RT)0;
       dvv[q] = (RT)0;
       if (q < K && tl * K + q < n) {
         const Rec<RT> rq = R.load(q * TL + tl);
         RT dv;
         const RT Kx = pair_kernel(pc, ri, rq, dv);
-        rij[q] = (double)swarm_rate(pc, ri, rq, Kx);
+        rij[q] = swarm_rate(pc, ri, rq, Kx);
         rji[q] = swarm_rate(pc, rq, ri, Kx);
         dvv[q] = dv;
-        part1 += rij[q];
       }
+      part1 += (double)rij[q];
     }
-    double excl1, Ri;
-    const double incl1 = tm.incl_scan(part1, excl1, Ri);
+    double Ri;
+    const double incl1 = tm.scan(part1, Ri);
     if (!(Ri > 0.0)) {
       // row i has no partner left (its stored sum was rounding residue):
       // clear it and count a null event
-      if (tl == ownI) {
+      if (tl == ci.lane) {
 #pragma unroll
         for (int q = 0; q < KMAX; ++q)
-          if (q == qI) r[q] = 0.0;
+          if (q == ci.q) r[q] = 0.0;
       }
       if (tl == 0 && A.evlog != nullptr && e < A.log_per_cell) {
         int32_t *L = A.evlog + ((size_t)cell * A.log_per_cell + e) * 4;
-        L[0] = ownI * K + qI;
+        L[0] = i_local;
         L[1] = -1;
         L[2] = -1;
         L[3] = 0;
       }
       ++e;
+      part = 0.0;
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q)
+        if (q < K) part += r[q];
+      incl = tm.scan(part, Rtot);
       continue;
     }
-    int ownJ;
-    double dvj;
-    const int qJ =
-        team_select<KMAX, T, RT>(tm, incl1, excl1, part1, rij, dvv, K, u3 * Ri, ownJ, dvj);
-    const int sj = qJ * TL + ownJ;
-    const double mj = R.m64[sj];
-    const int gj = R.idx[sj];
-    const int j_local = ownJ * K + qJ;
-    const int i_local = ownI * K + qI;
+    // -- choose j (payloads: m_j, relative velocity, index)
+    const Cand cj = team_pick<KMAX, RT, RT>(tm, incl1, part1, rij, K, u3 * Ri, m64, m64, dvv, gix);
+    const int j_local = cj.lane * K + cj.q;
+    const double mj = cj.p0;
+    const RT dvj = (RT)cj.p2;
+    const int gj = cj.gi;
 
     // -- outcome (only i changes)
     double mnew;
-    const bool fast = !((RT)dvj < (RT)A.P.v_frag);
+    const bool fast = !(dvj < (RT)A.P.v_frag);
     const int oc = outcome(A.P, fast, mi, mj, u4, mnew);
     if (!(mnew > 0.0) || !isfinite(mnew)) {
       if (tl == 0) atomicOr(&A.state->flags, FLAG_BAD_MASS);
@@ -295,15 +422,17 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
         tl < A.P.n_comp) {
       const double wi = mi, wj = group_factor(A.P.dm_max, mi, mj) * mj;
       float *cs = A.comp + (size_t)tl * A.N;
-      const double ci = (double)cs[gi], cj = (double)cs[gj];
-      cs[gi] = (float)((wi * ci + wj * cj) / (wi + wj));
+      const double cI = (double)cs[gi], cJ = (double)cs[gj];
+      cs[gi] = (float)((wi * cI + wj * cJ) / (wi + wj));
     }
-    const Rec<RT> rin = make_rec<RT>(A.P, g, mnew, Mi, scale);
-    tm.sync();  // every lane is done reading the old record of i
+    const Rec<RT> rin = RecAfter<RT>::get(A.P, tm.S, mnew, Mi);
+    if (tl == ci.lane) {
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q)
+        if (q == ci.q) m64[q] = mnew;
+    }
     if (tl == 0) {
       R.store(si, rin);
-      R.m64[si] = mnew;
-      A.m[gi] = mnew;
       if (A.evlog != nullptr && e < A.log_per_cell) {
         int32_t *L = A.evlog + ((size_t)cell * A.log_per_cell + e) * 4;
         L[0] = i_local;
@@ -312,7 +441,6 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
         L[3] = 0;
       }
     }
-    tm.sync();
 
     // -- new row i: incremental update of the other rows, fresh row sum of i
     double part2 = 0.0;
@@ -320,7 +448,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     for (int q = 0; q < KMAX; ++q) {
       if (q < K && tl * K + q < n) {
         const int s = q * TL + tl;
-        const Rec<RT> rq = R.load(s);
+        const Rec<RT> rq = s == si ? rin : R.load(s);
         RT dv;
         const RT Kx = pair_kernel(pc, rin, rq, dv);
         part2 += (double)swarm_rate(pc, rin, rq, Kx);
@@ -330,60 +458,84 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
         }
       }
     }
-    const double ri_new = tm.sum(part2);
-    if (tl == ownI) {
+    // next event's prefix of the row sums and the new r_i in one exchange;
+    // the owner's slot still holds the old r_i and is corrected afterwards
+    part = 0.0;
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q)
+      if (q < K) part += r[q];
+    double ri_new;
+    incl = tm.scan2(part, part2, Rtot, ri_new);
+    const double delta = ri_new - ri_old;
+    if (tl >= ci.lane) incl += delta;
+    Rtot += delta;
+    if (tl == ci.lane) {
+      part += delta;
 #pragma unroll
       for (int q = 0; q < KMAX; ++q)
-        if (q == qI) r[q] = ri_new;
+        if (q == ci.q) r[q] = ri_new;
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) oc_count[k] += (oc == k) ? 1ull : 0ull;
+    for (int k = 0; k < 4; ++k) oc_count[k] += (oc == k) ? 1u : 0u;
     ++e;
   }
+  // masses back to HBM
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q)
+    if (q < K && tl * K + q < n) A.m[gix[q]] = m64[q];
   if (tl == 0) {
     atomicAdd(&A.state->events, (unsigned long long)e);
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      if (oc_count[k]) atomicAdd(&A.state->outcomes[k], oc_count[k]);
+      if (oc_count[k]) atomicAdd(&A.state->outcomes[k], (unsigned long long)oc_count[k]);
   }
   tm.sync();  // the region is reused by the next cell
 }
 
 // ---------------------------------------------------------------------------
-// batched schedule: one persistent launch; big cells on four-wave teams
-// (largest first), then small cells on single waves (largest first)
+// batched schedule: one persistent launch of four-wave workgroups; big cells
+// on four-wave teams (largest first), then small cells on single waves
+// (largest first), each wave popping its own work
 // ---------------------------------------------------------------------------
-template <typename RT, int KBIG, int KSMALL>
-__global__ __launch_bounds__(256) void collide_batched(CollideArgs A) {
+template <typename RT, int KMAX>
+__global__ __launch_bounds__(256, 3) void collide_batched(CollideArgs A) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_item;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t step = A.state->step;
-  if (A.n_big > 0) {
-    for (;;) {
+  const size_t small_bytes = region_bytes<RT>(A.small_cap, 1);
+  int nw = A.n_big > 0 ? 4 : 1;
+  for (;;) {
+    int cell = -1;
+    if (nw == 4) {
       if (threadIdx.x == 0) s_item = atomicAdd(&A.state->big_head, 1);
       __syncthreads();
       const int item = s_item;
       __syncthreads();
-      if (item >= A.n_big) break;
-      process_cell<RT, KBIG, 4>(A, A.big_list[item], smem, A.big_cap, wave, lane, step);
+      if (item < A.n_big)
+        cell = A.big_list[item];
+      else
+        nw = 1;
     }
-  }
-  char *mine = smem + (size_t)wave * region_bytes<RT>(A.small_cap, 1);
-  for (;;) {
-    int item = 0;
-    if (lane == 0) item = atomicAdd(&A.state->small_head, 1);
-    item = __shfl(item, 0, 64);
-    if (item >= A.n_small) break;
-    process_cell<RT, KSMALL, 1>(A, A.small_list[item], mine, A.small_cap, 0, lane, step);
+    if (nw == 1) {
+      int item = 0;
+      if (lane == 0) item = atomicAdd(&A.state->small_head, 1);
+      item = readlane_i(item, 0);
+      if (item >= A.n_small) break;
+      cell = A.small_list[item];
+    }
+    char *base = nw == 4 ? smem : smem + (size_t)wave * small_bytes;
+    process_cell<RT, KMAX>(A, cell, base, nw == 4 ? A.big_cap : A.small_cap, nw,
+                           nw == 4 ? wave : 0, lane, step);
   }
 }
 
-// plain schedule: one one-wave workgroup per cell
+// plain schedule: one four-wave workgroup per cell, cells in index order
 template <typename RT, int KMAX>
-__global__ __launch_bounds__(64) void collide_plain(CollideArgs A) {
+__global__ __launch_bounds__(256) void collide_plain(CollideArgs A) {
   extern __shared__ __align__(16) char smem[];
-  process_cell<RT, KMAX, 1>(A, blockIdx.x, smem, A.small_cap, 0, threadIdx.x, A.state->step);
+  process_cell<RT, KMAX>(A, blockIdx.x, smem, A.big_cap, 4, threadIdx.x >> 6, threadIdx.x & 63,
+                         A.state->step);
 }
 
 __global__ void reset_queues(DevState *st) {
@@ -432,17 +584,21 @@ __global__ __launch_bounds__(256) void rates_cell(CollideArgs A, int cell, doubl
 }
 
 // ---------------------------------------------------------------------------
-template <typename RT, int KB, int KS>
+template <typename Kern>
+static hipError_t prepare(Kern kern, size_t lds) {
+  if (lds > 64 * 1024)
+    return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+  return hipSuccess;
+}
+
+template <typename RT, int KMAX>
 static hipError_t run_batched(const CollideArgs &a, int grid_override, hipStream_t s) {
   const size_t lds = std::max(region_bytes<RT>(a.big_cap, 4), 4 * region_bytes<RT>(a.small_cap, 1));
-  auto kern = collide_batched<RT, KB, KS>;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
+  auto kern = collide_batched<RT, KMAX>;
+  hipError_t e = prepare(kern, lds);
   int dev = 0, cus = 0, per_cu = 0;
-  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, 256, lds);
@@ -456,31 +612,29 @@ static hipError_t run_batched(const CollideArgs &a, int grid_override, hipStream
   return hipGetLastError();
 }
 
-template <typename RT>
+template <typename RT, int KMAX>
 static hipError_t run_plain(const CollideArgs &a, int n_cells, hipStream_t s) {
-  const size_t lds = region_bytes<RT>(a.small_cap, 1);
-  auto kern = collide_plain<RT, 16>;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  if (n_cells > 0) kern<<<n_cells, 64, lds, s>>>(a);
+  const size_t lds = region_bytes<RT>(a.big_cap, 4);
+  auto kern = collide_plain<RT, KMAX>;
+  hipError_t e = prepare(kern, lds);
+  if (e != hipSuccess) return e;
+  if (n_cells > 0) kern<<<n_cells, 256, lds, s>>>(a);
   return hipGetLastError();
 }
 
 hipError_t launch_collide(const CollideArgs &a, int precision, int schedule, int n_cells,
                           int max_cell, int grid_override, hipStream_t s) {
+  const bool wide = max_cell > 1024;
   if (schedule == 0) {
-    if (max_cell > 64 * 16) return hipErrorInvalidValue;
-    return precision == 0 ? run_plain<double>(a, n_cells, s) : run_plain<float>(a, n_cells, s);
+    if (precision == 0)
+      return wide ? run_plain<double, 8>(a, n_cells, s) : run_plain<double, 4>(a, n_cells, s);
+    return wide ? run_plain<float, 8>(a, n_cells, s) : run_plain<float, 4>(a, n_cells, s);
   }
-  const bool wide = a.big_cap > 256 * 4;
   if (precision == 0)
-    return wide ? run_batched<double, 8, 4>(a, grid_override, s)
-                : run_batched<double, 4, 4>(a, grid_override, s);
-  return wide ? run_batched<float, 8, 4>(a, grid_override, s)
-              : run_batched<float, 4, 4>(a, grid_override, s);
+    return wide ? run_batched<double, 8>(a, grid_override, s)
+                : run_batched<double, 4>(a, grid_override, s);
+  return wide ? run_batched<float, 8>(a, grid_override, s)
+              : run_batched<float, 4>(a, grid_override, s);
 }
 
 hipError_t launch_rates_cell(const CollideArgs &a, int precision, int cell, double *r_out,

@@ -1,5 +1,5 @@
-// device_common.hpp -- counter-based random numbers and wavefront / team
-// primitives for gfx950 (wave64).
+// device_common.hpp -- counter-based random numbers and wavefront primitives
+// for gfx950 (wave64): DPP prefix scans, ballots, lane reads, LDS fences.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -44,158 +44,60 @@ __host__ __device__ inline double u01(uint32_t lo, uint32_t hi) {
 // ---------------------------------------------------------------------------
 __device__ inline int lane_id() { return (int)__lane_id(); }
 
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+// order LDS accesses of the lanes of one wave
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
   __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
-__device__ inline double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
+// workgroup barrier that orders LDS only (global memory is not waited for)
+__device__ inline void block_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-__device__ inline double wave_max(double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
-  return x;
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ inline double dpp_d(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, BANK_MASK, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, BANK_MASK, true);
+  return __hiloint2double(hi, lo);
 }
 
+__device__ inline double readlane_d(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ inline int readlane_i(int x, int lane) { return __builtin_amdgcn_readlane(x, lane); }
+
+// inclusive prefix sum over the 64 lanes: shifts of 1, 2, 4, 8 inside rows of
+// 16 lanes, then row broadcasts of lanes 15 and 31 (gfx9 DPP)
 __device__ inline double wave_incl_scan(double x) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const double y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
+  x += dpp_d<0x111, 0xf, 0xf>(x);  // row_shr:1
+  x += dpp_d<0x112, 0xf, 0xf>(x);  // row_shr:2
+  x += dpp_d<0x114, 0xf, 0xf>(x);  // row_shr:4
+  x += dpp_d<0x118, 0xf, 0xf>(x);  // row_shr:8
+  x += dpp_d<0x142, 0xa, 0xf>(x);  // row_bcast:15 into rows 1, 3
+  x += dpp_d<0x143, 0xc, 0xf>(x);  // row_bcast:31 into rows 2, 3
   return x;
 }
 
-// ---------------------------------------------------------------------------
-// A team is T consecutive waves of one workgroup working on one cell.
-// T == 1 needs no barrier (a wave runs in lockstep); T > 1 synchronises the
-// whole workgroup, so every wave of the workgroup must belong to the team.
-// scratch: LDS area of at least 8*T doubles + 4*T ints.
-// ---------------------------------------------------------------------------
-template <int T>
-struct Team {
-  int wave;       // wave index inside the team
-  int lane;       // lane inside the wave
-  int tl;         // team lane = wave*64 + lane
-  double *red;    // 2 x 2T doubles (double-buffered)
-  int *ired;      // 2 x 2T ints
-  int phase;
+// maximum over the 64 lanes (non-negative inputs), returned on every lane
+__device__ inline double wave_max_nonneg(double x) {
+  x = fmax(x, dpp_d<0x111, 0xf, 0xf>(x));
+  x = fmax(x, dpp_d<0x112, 0xf, 0xf>(x));
+  x = fmax(x, dpp_d<0x114, 0xf, 0xf>(x));
+  x = fmax(x, dpp_d<0x118, 0xf, 0xf>(x));
+  x = fmax(x, dpp_d<0x142, 0xa, 0xf>(x));
+  x = fmax(x, dpp_d<0x143, 0xc, 0xf>(x));
+  return readlane_d(x, 63);
+}
 
-  __device__ Team(int wave_, int lane_, void *scratch)
-      : wave(wave_), lane(lane_), tl(wave_ * 64 + lane_), red((double *)scratch),
-        ired((int *)((double *)scratch + 4 * T)), phase(0) {}
-
-  __device__ void sync() {
-    if (T > 1)
-      __syncthreads();
-    else
-      wave_sync();
-  }
-
-  __device__ double sum(double x) {
-    x = wave_sum(x);
-    if (T == 1) return x;
-    phase ^= 1;
-    double *buf = red + phase * 2 * T;
-    if (lane == 0) buf[wave] = x;
-    __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < T; ++w) s += buf[w];
-    return s;
-  }
-
-  __device__ double max(double x) {
-    x = wave_max(x);
-    if (T == 1) return x;
-    phase ^= 1;
-    double *buf = red + phase * 2 * T;
-    if (lane == 0) buf[wave] = x;
-    __syncthreads();
-    double s = buf[0];
-#pragma unroll
-    for (int w = 1; w < T; ++w) s = fmax(s, buf[w]);
-    return s;
-  }
-
-  // inclusive scan over team lanes; also returns the exclusive prefix and
-  // the total (identical on every lane)
-  __device__ double incl_scan(double x, double &excl, double &total) {
-    double inc = wave_incl_scan(x);
-    double prev = __shfl_up(inc, 1, 64);
-    if (lane == 0) prev = 0.0;
-    if (T == 1) {
-      total = __shfl(inc, 63, 64);
-      excl = prev;
-      return inc;
-    }
-    phase ^= 1;
-    double *buf = red + phase * 2 * T;
-    if (lane == 63) buf[wave] = inc;
-    __syncthreads();
-    double off = 0.0, tot = 0.0;
-#pragma unroll
-    for (int w = 0; w < T; ++w) {
-      if (w < wave) off += buf[w];
-      tot += buf[w];
-    }
-    total = tot;
-    excl = off + prev;
-    return off + inc;
-  }
-
-  // first team lane with pred set (or -1); on a miss, the last team lane
-  // with fallback set (or -1) goes into *fb
-  __device__ int first_lane(bool pred, bool fallback, int *fb) {
-    const uint64_t b = __ballot(pred);
-    const uint64_t f = __ballot(fallback);
-    if (T == 1) {
-      *fb = f ? 63 - __clzll(f) : -1;
-      return b ? __ffsll((unsigned long long)b) - 1 : -1;
-    }
-    phase ^= 1;
-    int *buf = ired + phase * 2 * T;
-    if (lane == 0) {
-      buf[wave] = b ? __ffsll((unsigned long long)b) - 1 : -1;
-      buf[T + wave] = f ? 63 - __clzll(f) : -1;
-    }
-    __syncthreads();
-    int first = -1, last = -1;
-#pragma unroll
-    for (int w = T - 1; w >= 0; --w) {
-      if (buf[w] >= 0) first = w * 64 + buf[w];
-    }
-#pragma unroll
-    for (int w = 0; w < T; ++w) {
-      if (buf[T + w] >= 0) last = w * 64 + buf[T + w];
-    }
-    *fb = last;
-    return first;
-  }
-
-  // broadcast an int and a double from team lane `src`
-  __device__ void bcast(int src, int &iv, double &dv) {
-    if (T == 1) {
-      iv = __shfl(iv, src, 64);
-      dv = __shfl(dv, src, 64);
-      return;
-    }
-    phase ^= 1;
-    int *ib = ired + phase * 2 * T;
-    double *db = red + phase * 2 * T;
-    if (tl == src) {
-      ib[0] = iv;
-      db[0] = dv;
-    }
-    __syncthreads();
-    iv = ib[0];
-    dv = db[0];
-  }
-};
+__device__ inline uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ inline int first_set(uint64_t b) { return b ? __builtin_ctzll(b) : -1; }
+__device__ inline int last_set(uint64_t b) { return b ? 63 - __builtin_clzll(b) : -1; }
 
 }  // namespace mcd

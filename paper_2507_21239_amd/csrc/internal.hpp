@@ -48,11 +48,31 @@ struct CollideArgs {
   int64_t log_per_cell;
 };
 
-// LDS bytes of one team region holding `cap` particles
+// a selection result: payloads of the chosen slot, its slot and team lane
+struct Cand {
+  double p0, p1, p2;
+  int q, lane, hit, gi;
+};
+
+// team scratch after a region's particle records: wave totals, selection
+// candidates of each wave (double-buffered) and the cell's gas state
+struct TeamScratch {
+  double tot[2][8];
+  Cand cand[2][4];
+  Gas gas;
+  CellF cf;
+};
+
+// LDS bytes of one particle record in rate precision RT
 template <typename RT>
-constexpr size_t region_bytes(int cap, int T) {
-  // ten RT arrays + m, M (double) + index (int) + team scratch
-  return (size_t)cap * (10 * sizeof(RT) + 2 * sizeof(double) + sizeof(int32_t)) + 64 * T + 64;
+constexpr size_t rec_bytes() {
+  return 10 * sizeof(RT);
+}
+
+// LDS bytes of one team region holding `cap` particles (16-byte multiple)
+template <typename RT>
+constexpr size_t region_bytes(int cap, int /*waves*/) {
+  return ((size_t)cap * rec_bytes<RT>() + sizeof(TeamScratch) + 15) / 16 * 16;
 }
 
 // launchers (collide.hip)

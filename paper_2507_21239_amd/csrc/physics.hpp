@@ -137,6 +137,34 @@ __host__ __device__ inline Rec<RT> make_rec(const Model &P, const Gas &g, double
   return o;
 }
 
+// per-cell constants of the FP32 particle state (mixed precision): the
+// same formulas as make_rec with the cell factors folded in single precision
+struct CellF {
+  float ca;     // 3 / (4 pi rho_s)
+  float a_sw;   // Epstein / Stokes switch radius 9 lambda / 4
+  float tE;     // Epstein stopping time per unit radius rho_s / (rho_g v_th)
+  float tS;     // Stokes stopping time per unit radius^2 2 rho_s / (9 nu rho_g)
+  float Om, Ste, m2eta, meta, mzO;
+  float pad;
+  double nd_fac;  // rate scale / V
+};
+
+__host__ __device__ inline CellF make_cellf(const Model &P, const Gas &g, double scale) {
+  CellF c;
+  c.ca = (float)(3.0 / (4.0 * kPi * P.rho_s));
+  c.a_sw = (float)(2.25 * g.lambda);
+  c.tE = (float)(P.rho_s / (g.rho_g * g.v_th));
+  c.tS = (float)(2.0 * P.rho_s / (9.0 * g.nu * g.rho_g));
+  c.Om = (float)g.Omega;
+  c.Ste = (float)g.St_eta;
+  c.m2eta = (float)(-2.0 * g.eta_vK);
+  c.meta = (float)(-g.eta_vK);
+  c.mzO = (float)(-g.z_c * g.Omega);
+  c.pad = 0.0f;
+  c.nd_fac = scale / g.V;
+  return c;
+}
+
 // per-cell constants of the pair rate
 template <typename RT>
 struct PairConst {
@@ -144,6 +172,7 @@ struct PairConst {
   RT Vg2;      // large-eddy velocity squared
   RT St_eta;   // Kolmogorov Stokes number Re^-1/2
   RT dm_max;
+  RT inv_dm;   // 1 / dm_max (0 when grouping is off)
   RT k0;
   uint32_t flags;
   int32_t kernel;
@@ -156,10 +185,33 @@ __host__ __device__ inline PairConst<RT> make_pair_const(const Model &P, const G
   c.Vg2 = (RT)g.Vg2;
   c.St_eta = (RT)g.St_eta;
   c.dm_max = (RT)P.dm_max;
+  c.inv_dm = P.dm_max > 0.0 ? (RT)(1.0 / P.dm_max) : (RT)0;
   c.k0 = (RT)P.k0;
   c.flags = P.flags;
   c.kernel = P.kernel;
   return c;
+}
+
+// FP32 particle state of the mixed path (after a collision changed m)
+__device__ inline Rec<float> make_rec_f(const CellF &c, double m, double M) {
+  const float mf = (float)m;
+  const float a = cbrtf(mf * c.ca);
+  const float ts = a < c.a_sw ? c.tE * a : c.tS * a * a;
+  const float St = ts * c.Om;
+  const float q1 = __builtin_amdgcn_rcpf(1.0f + St);
+  const float w = __builtin_amdgcn_rcpf(1.0f + St * St);
+  Rec<float> r;
+  r.m = mf;
+  r.im = __builtin_amdgcn_rcpf(mf);
+  r.a = a;
+  r.St = St;
+  r.h = St * St * __builtin_amdgcn_rcpf(St + c.Ste);
+  r.q1 = q1;
+  r.vr = c.m2eta * St * w;
+  r.vp = c.meta * w;
+  r.vz = c.mzO * St * q1;
+  r.nd = (float)(M * c.nd_fac) * r.im;
+  return r;
 }
 
 // precision-specific division and square root: FP64 correctly rounded;
@@ -230,13 +282,20 @@ __device__ inline RT pair_kernel(const PairConst<RT> &c, const Rec<RT> &x, const
 
 // rate of representative particle x against swarm y given K_xy:
 // n_y K / max(1, dm_max m_x / m_y)
-template <typename RT>
-__device__ inline RT swarm_rate(const PairConst<RT> &c, const Rec<RT> &x, const Rec<RT> &y, RT K) {
-  RT r = y.nd * K;
-  if (c.dm_max > (RT)0) {
-    RT grp = pdiv(c.dm_max * x.m, y.m);
-    if (grp > (RT)1) r = pdiv(r, grp);
+__device__ inline double swarm_rate(const PairConst<double> &c, const Rec<double> &x,
+                                    const Rec<double> &y, double K) {
+  double r = y.nd * K;
+  if (c.dm_max > 0.0) {
+    const double grp = c.dm_max * x.m / y.m;
+    if (grp > 1.0) r = r / grp;
   }
+  return r;
+}
+// FP32: the same factor as n_y K min(1, m_y / (dm_max m_x)), no reciprocal
+__device__ inline float swarm_rate(const PairConst<float> &c, const Rec<float> &x,
+                                   const Rec<float> &y, float K) {
+  float r = y.nd * K;
+  if (c.dm_max > 0.0f) r *= fminf(1.0f, y.m * (x.im * c.inv_dm));
   return r;
 }
 

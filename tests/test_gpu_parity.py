@@ -2,12 +2,12 @@
 C ABI, on identical seeded inputs.
 
 Bars: integer and index results (Philox words, binning, event sequences)
-bit-exact; FP64 floating point within 1e-12 relative (the two sides use
+bit-exact; FP64 masses and positions within 1e-12 relative (the two sides use
 different cbrt / pow / exp / log libraries and different summation orders,
-each good to a few ulps; the pair rate is a short product of such values);
-FP32 rates within 1e-4 relative (single-precision pair arithmetic with the
-hardware reciprocal and square root, about 1e-6, plus FP32 accumulation of up
-to 2048 terms)."""
+each good to a few ulps); rate matrices row-normwise (|r_ij - r_ij'| / r_i)
+within 1e-13 in FP64 and 1e-5 with FP32 pair rates (single-precision pair
+arithmetic with the hardware reciprocal and square root, ~1e-7 per
+operation, plus FP32 accumulation of up to 2048 terms)."""
 import numpy as np
 import pytest
 
@@ -70,13 +70,18 @@ def test_binning_bit_exact(N, n_r, n_z, seed):
 
 
 def _rates_check(precision, tol):
+    """Row-normwise error max_j |r_ij - r_ij^oracle| / r_i: the method only
+    uses r_ij through the selection probabilities r_ij / r_i and the row
+    sums.  The elementwise relative error is reported too; it is larger for
+    pairs of near-identical particles, whose relative velocity is a small
+    difference of large drift velocities (cancellation)."""
     api = _api()
     work = edge_size_work()
     dev = api.to_device(work["particles"])
     sim = api.Simulation(work["params"], dev, precision=precision)
     sim.bin(api.cells_to_device(work["cells"]))
     cs = work["cells"]["cell_start"]
-    worst = 0.0
+    worst_row = worst_el = 0.0
     for c in range(len(cs) - 1):
         n = int(cs[c + 1] - cs[c])
         if n == 0:
@@ -88,22 +93,28 @@ def _rates_check(precision, tol):
         Ro, rso = O.cell_rates(work["params"], work["cells"]["gas"][c], members,
                                work["particles"]["m"], work["particles"]["M"])
         assert np.all(Ro > 0)
-        err = np.max(np.abs(Rg - Ro) / Ro)
+        row = np.max(np.abs(Rg - Ro) / rso[:, None])
+        el = np.abs(Rg - Ro) / Ro
         err_rs = np.max(np.abs(rsg - rso) / rso)
-        worst = max(worst, err, err_rs)
-        assert err <= tol and err_rs <= tol, (c, n, err, err_rs)
+        if el.max() > worst_el:
+            i, j = np.unravel_index(np.argmax(el), el.shape)
+            m = work["particles"]["m"][members]
+            say("worst element", (i, j), "rel", el[i, j], "m_i/m_j", m[i] / m[j],
+                "share of row", Ro[i, j] / rso[i])
+        worst_row, worst_el = max(worst_row, row, err_rs), max(worst_el, el.max())
+        assert row <= tol and err_rs <= tol, (c, n, row, err_rs)
     sim.close()
-    return worst
+    return worst_row, worst_el
 
 
 def test_rates_fp64_match_oracle():
-    worst = _rates_check("fp64", 1e-12)
-    say("fp64 rate max rel err", worst)
+    row, el = _rates_check("fp64", 1e-13)
+    say("fp64 rate error: row-normwise", row, "elementwise", el)
 
 
 def test_rates_mixed_within_fp32_tolerance():
-    worst = _rates_check("mixed", 1e-4)
-    say("mixed rate max rel err", worst)
+    row, el = _rates_check("mixed", 1e-5)
+    say("mixed rate error: row-normwise", row, "elementwise", el)
 
 
 @pytest.mark.parametrize("schedule", ["plain", "batched"])
