@@ -32,36 +32,35 @@ template <>
 struct RecStore<float> {
   float4 *A;  // im, a, St, h
   float4 *B;  // q1, vr, vp, vz
-  float2 *C;  // nd, m
+  float4 *C;  // nd, m, ist, -
   __device__ RecStore(char *base, int cap)
-      : A((float4 *)base), B((float4 *)base + cap), C((float2 *)((float4 *)base + 2 * cap)) {}
+      : A((float4 *)base), B((float4 *)base + cap), C((float4 *)base + 2 * cap) {}
   __device__ Rec<float> load(int s) const {
-    const float4 a = A[s], b = B[s];
-    const float2 c = C[s];
+    const float4 a = A[s], b = B[s], c = C[s];
     Rec<float> r;
     r.im = a.x; r.a = a.y; r.St = a.z; r.h = a.w;
     r.q1 = b.x; r.vr = b.y; r.vp = b.z; r.vz = b.w;
-    r.nd = c.x; r.m = c.y;
+    r.nd = c.x; r.m = c.y; r.ist = c.z;
     return r;
   }
   __device__ void store(int s, const Rec<float> &r) const {
     A[s] = make_float4(r.im, r.a, r.St, r.h);
     B[s] = make_float4(r.q1, r.vr, r.vp, r.vz);
-    C[s] = make_float2(r.nd, r.m);
+    C[s] = make_float4(r.nd, r.m, r.ist, 0.0f);
   }
 };
 
 template <>
 struct RecStore<double> {
-  double2 *D;  // 5 arrays: (im, a) (St, h) (q1, vr) (vp, vz) (nd, m)
+  double2 *D;  // 6 arrays: (im, a) (St, h) (q1, vr) (vp, vz) (nd, m) (ist, -)
   int cap;
   __device__ RecStore(char *base, int cap_) : D((double2 *)base), cap(cap_) {}
   __device__ Rec<double> load(int s) const {
     const double2 a = D[s], b = D[cap + s], c = D[2 * cap + s], d = D[3 * cap + s],
-                  e = D[4 * cap + s];
+                  e = D[4 * cap + s], f = D[5 * cap + s];
     Rec<double> r;
     r.im = a.x; r.a = a.y; r.St = b.x; r.h = b.y; r.q1 = c.x; r.vr = c.y;
-    r.vp = d.x; r.vz = d.y; r.nd = e.x; r.m = e.y;
+    r.vp = d.x; r.vz = d.y; r.nd = e.x; r.m = e.y; r.ist = f.x;
     return r;
   }
   __device__ void store(int s, const Rec<double> &r) const {
@@ -70,6 +69,36 @@ struct RecStore<double> {
     D[2 * cap + s] = make_double2(r.q1, r.vr);
     D[3 * cap + s] = make_double2(r.vp, r.vz);
     D[4 * cap + s] = make_double2(r.nd, r.m);
+    D[5 * cap + s] = make_double2(r.ist, 0.0);
+  }
+};
+
+// record of an empty slot: zero number density, so every rate against it
+// vanishes; finite values elsewhere
+template <typename RT>
+__device__ inline Rec<RT> empty_rec() {
+  Rec<RT> r;
+  r.m = r.im = r.St = r.ist = (RT)1;
+  r.a = r.h = r.vr = r.vp = r.vz = r.nd = (RT)0;
+  r.q1 = (RT)0.5;
+  return r;
+}
+
+// both directed rates of a pair and the relative velocity
+template <typename RT, bool FAST>
+struct PairEval {
+  __device__ static void run(const PairConst<RT> &c, const Rec<RT> &x, const Rec<RT> &y, RT &dv,
+                             RT &rxy, RT &ryx) {
+    const RT K = pair_kernel(c, x, y, dv);
+    rxy = swarm_rate(c, x, y, K);
+    ryx = swarm_rate(c, y, x, K);
+  }
+};
+template <>
+struct PairEval<float, true> {
+  __device__ static void run(const PairConst<float> &c, const Rec<float> &x, const Rec<float> &y,
+                             float &dv, float &rxy, float &ryx) {
+    pair_rates_all(c, x, y, dv, rxy, ryx);
   }
 };
 
@@ -167,52 +196,43 @@ __device__ inline Cand team_pick(Team &tm, double incl, double part, const VT *v
   const uint64_t bh = ballot(hit), bf = ballot(part > 0.0);
   const int first = first_set(bh);
   const int src = first >= 0 ? first : last_set(bf);
-  Cand c{0.0, 0.0, 0.0, -1, -1, first >= 0 ? 1 : 0, -1};
-  if (tm.lane == src) {
-    double cum = incl - part;
-    int last = -1;
-    bool found = false;
-    int qsel = -1;
+  // every lane searches its own slots as if it owned the pick (no divergent
+  // code); the owner's answer is read afterwards
+  double cum = incl - part;
+  int qhit = -1, last = -1;
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q) {
-      if (q < K && !found) {
-        if (v[q] > (VT)0) last = q;
-        cum += (double)v[q];
-        if (first >= 0 && cum > target) {
-          qsel = q;
-          found = true;
-        }
-      }
+  for (int q = 0; q < KMAX; ++q) {
+    if (q < K) {
+      last = v[q] > (VT)0 ? q : last;
+      cum += (double)v[q];
+      qhit = (qhit < 0 && cum > target) ? q : qhit;
     }
-    if (!found) qsel = last;
-#pragma unroll
-    for (int q = 0; q < KMAX; ++q) {
-      if (q == qsel) {
-        c.p0 = a0[q];
-        c.p1 = a1[q];
-        c.p2 = (double)a2[q];
-        c.gi = ai[q];
-      }
-    }
-    c.q = qsel;
-    c.lane = tm.tl;
   }
-  if (tm.nw == 1) {
-    Cand o{0.0, 0.0, 0.0, -1, -1, 0, -1};
-    if (src < 0) return o;
-    o.q = readlane_i(c.q, src);
-    o.lane = src;
-    o.hit = first >= 0 ? 1 : 0;
-    o.gi = readlane_i(c.gi, src);
-    o.p0 = readlane_d(c.p0, src);
-    o.p1 = readlane_d(c.p1, src);
-    o.p2 = readlane_d(c.p2, src);
-    return o;
+  const int qsel = (first >= 0 && qhit >= 0) ? qhit : last;
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+  int gi = -1;
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    const bool m = q == qsel;
+    p0 = m ? a0[q] : p0;
+    p1 = m ? a1[q] : p1;
+    p2 = m ? (double)a2[q] : p2;
+    gi = m ? ai[q] : gi;
+  }
+  Cand o{0.0, 0.0, 0.0, -1, -1, first >= 0 ? 1 : 0, -1};
+  if (src < 0) {
+    if (tm.nw == 1) return o;
+  } else {
+    o.q = readlane_i(qsel, src);
+    o.lane = tm.wave * 64 + src;
+    o.gi = readlane_i(gi, src);
+    o.p0 = readlane_d(p0, src);
+    o.p1 = readlane_d(p1, src);
+    o.p2 = readlane_d(p2, src);
+    if (tm.nw == 1) return o;
   }
   tm.phase ^= 1;
-  Cand *slot = &tm.S->cand[tm.phase][tm.wave];
-  if (tm.lane == 0 && src < 0) slot->q = -1;
-  if (tm.lane == src) *slot = c;
+  if (tm.lane == 0) tm.S->cand[tm.phase][tm.wave] = o;
   block_lds_sync();
   int wsel = -1;
   for (int w = tm.nw - 1; w >= 0; --w) {
@@ -224,13 +244,13 @@ __device__ inline Cand team_pick(Team &tm, double incl, double part, const VT *v
       if (tm.S->cand[tm.phase][w].q >= 0) wsel = w;
   }
   if (wsel < 0) {
-    Cand o{0.0, 0.0, 0.0, -1, -1, 0, -1};
-    return o;
+    Cand z{0.0, 0.0, 0.0, -1, -1, 0, -1};
+    return z;
   }
   return tm.S->cand[tm.phase][wsel];
 }
 
-template <typename RT, int KMAX>
+template <typename RT, int KMAX, bool FAST>
 __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap, int nw, int wave,
                              int lane, uint32_t step) {
   const int s0 = A.cell_start[cell];
@@ -291,9 +311,14 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     tm.S->gas = g;
     tm.S->cf = make_cellf(A.P, g, scale);
   }
+  uint32_t valid = 0;  // bit q: slot q holds a particle
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) {
-    if (q < K && tl * K + q < n) R.store(q * TL + tl, make_rec<RT>(A.P, g, m64[q], A.M[gix[q]], scale));
+    if (q < K) {
+      const bool v = tl * K + q < n;
+      valid |= v ? (1u << q) : 0u;
+      R.store(q * TL + tl, v ? make_rec<RT>(A.P, g, m64[q], A.M[gix[q]], scale) : empty_rec<RT>());
+    }
   }
   tm.sync();
 
@@ -311,9 +336,9 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
       for (int q2 = 0; q2 < K; ++q2) {
         if (t2 * K + q2 >= n) break;
         const Rec<RT> rk = R.load(q2 * TL + t2);
-        RT dv;
-        const RT Kx = pair_kernel(pc, mine, rk, dv);
-        acc += swarm_rate(pc, mine, rk, Kx);
+        RT dv, rxy, ryx;
+        PairEval<RT, FAST>::run(pc, mine, rk, dv, rxy, ryx);
+        acc += rxy;
       }
     }
 #pragma unroll
@@ -332,20 +357,32 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
   for (int q = 0; q < KMAX; ++q)
     if (q < K) part += r[q];
   double incl = tm.scan(part, Rtot);
+  // random words of 64 consecutive events: lane l holds Philox(e0 + l, cell,
+  // step, 0) and Philox(e0 + l, cell, step, 1); an event reads its lane
+  U4 rw0{0u, 0u, 0u, 0u}, rw1{0u, 0u, 0u, 0u};
+  int64_t e0 = -64;
   for (;;) {
     if (!(Rtot > 0.0) || !isfinite(Rtot)) {
       if (!isfinite(Rtot) && tl == 0) atomicOr(&A.state->flags, FLAG_BAD_RATE);
       break;
     }
     if (A.max_events > 0 && e >= A.max_events) break;
-    const U4 w0 = philox4x32_10(U4{(uint32_t)e, c32, step, 0u}, A.P.key0, A.P.key1);
-    const U4 w1 = philox4x32_10(U4{(uint32_t)e, c32, step, 1u}, A.P.key0, A.P.key1);
+    if (e - e0 >= 64) {
+      e0 = e;
+      const uint32_t ec = (uint32_t)(e + lane);
+      rw0 = philox4x32_10(U4{ec, c32, step, 0u}, A.P.key0, A.P.key1);
+      rw1 = philox4x32_10(U4{ec, c32, step, 1u}, A.P.key0, A.P.key1);
+    }
+    const int rl = (int)(e - e0);
     if (timed) {
-      const double tau = -log(u01(w0.x, w0.y)) / Rtot * scale;  // exponential waiting time
+      const double u1 = u01((uint32_t)readlane_i((int)rw0.x, rl), (uint32_t)readlane_i((int)rw0.y, rl));
+      const double tau = -log(u1) / Rtot * scale;  // exponential waiting time
       if (t + tau > A.dt) break;  // the next event falls outside the step
       t += tau;
     }
-    const double u2 = u01(w0.z, w0.w), u3 = u01(w1.x, w1.y), u4 = u01(w1.z, w1.w);
+    const double u2 = u01((uint32_t)readlane_i((int)rw0.z, rl), (uint32_t)readlane_i((int)rw0.w, rl));
+    const double u3 = u01((uint32_t)readlane_i((int)rw1.x, rl), (uint32_t)readlane_i((int)rw1.y, rl));
+    const double u4 = u01((uint32_t)readlane_i((int)rw1.z, rl), (uint32_t)readlane_i((int)rw1.w, rl));
 
     // -- choose i by cumulative row sums (payloads: m_i, index)
     const Cand ci = team_pick<KMAX, double, double>(tm, incl, part, r, K, u2 * Rtot, m64, r, m64,
@@ -369,13 +406,9 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
       rij[q] = (RT)0;
       rji[q] = (RT)0;
       dvv[q] = (RT)0;
-      if (q < K && tl * K + q < n) {
+      if (q < K) {  // empty slots have zero density: rij = 0
         const Rec<RT> rq = R.load(q * TL + tl);
-        RT dv;
-        const RT Kx = pair_kernel(pc, ri, rq, dv);
-        rij[q] = swarm_rate(pc, ri, rq, Kx);
-        rji[q] = swarm_rate(pc, rq, ri, Kx);
-        dvv[q] = dv;
+        PairEval<RT, FAST>::run(pc, ri, rq, dvv[q], rij[q], rji[q]);
       }
       part1 += (double)rij[q];
     }
@@ -446,16 +479,15 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     double part2 = 0.0;
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) {
-      if (q < K && tl * K + q < n) {
+      if (q < K) {
         const int s = q * TL + tl;
         const Rec<RT> rq = s == si ? rin : R.load(s);
-        RT dv;
-        const RT Kx = pair_kernel(pc, rin, rq, dv);
-        part2 += (double)swarm_rate(pc, rin, rq, Kx);
-        if (s != si) {
-          const double x = (r[q] - (double)rji[q]) + (double)swarm_rate(pc, rq, rin, Kx);
-          r[q] = x > 0.0 ? x : 0.0;
-        }
+        RT dv, a_iq, a_qi;
+        PairEval<RT, FAST>::run(pc, rin, rq, dv, a_iq, a_qi);
+        part2 += (double)a_iq;
+        const double x = (r[q] - (double)rji[q]) + (double)a_qi;
+        const bool upd = s != si && ((valid >> q) & 1u);
+        r[q] = upd ? (x > 0.0 ? x : 0.0) : r[q];
       }
     }
     // next event's prefix of the row sums and the new r_i in one exchange;
@@ -497,8 +529,8 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
 // on four-wave teams (largest first), then small cells on single waves
 // (largest first), each wave popping its own work
 // ---------------------------------------------------------------------------
-template <typename RT, int KMAX>
-__global__ __launch_bounds__(256, 3) void collide_batched(CollideArgs A) {
+template <typename RT, int KMAX, bool FAST>
+__global__ __launch_bounds__(256, sizeof(RT) == 4 ? 3 : 2) void collide_batched(CollideArgs A) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_item;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -525,16 +557,16 @@ __global__ __launch_bounds__(256, 3) void collide_batched(CollideArgs A) {
       cell = A.small_list[item];
     }
     char *base = nw == 4 ? smem : smem + (size_t)wave * small_bytes;
-    process_cell<RT, KMAX>(A, cell, base, nw == 4 ? A.big_cap : A.small_cap, nw,
-                           nw == 4 ? wave : 0, lane, step);
+    process_cell<RT, KMAX, FAST>(A, cell, base, nw == 4 ? A.big_cap : A.small_cap, nw,
+                                 nw == 4 ? wave : 0, lane, step);
   }
 }
 
 // plain schedule: one four-wave workgroup per cell, cells in index order
-template <typename RT, int KMAX>
+template <typename RT, int KMAX, bool FAST>
 __global__ __launch_bounds__(256) void collide_plain(CollideArgs A) {
   extern __shared__ __align__(16) char smem[];
-  process_cell<RT, KMAX>(A, blockIdx.x, smem, A.big_cap, 4, threadIdx.x >> 6, threadIdx.x & 63,
+  process_cell<RT, KMAX, FAST>(A, blockIdx.x, smem, A.big_cap, 4, threadIdx.x >> 6, threadIdx.x & 63,
                          A.state->step);
 }
 
@@ -547,7 +579,7 @@ __global__ void reset_queues(DevState *st) {
 // test path: the full rate matrix of one cell, from the same records and
 // pair code as the collision kernel
 // ---------------------------------------------------------------------------
-template <typename RT>
+template <typename RT, bool FAST>
 __global__ __launch_bounds__(256) void rates_cell(CollideArgs A, int cell, double *r_out,
                                                   int64_t ld, double *rowsum) {
   const int s0 = A.cell_start[cell];
@@ -573,9 +605,8 @@ __global__ __launch_bounds__(256) void rates_cell(CollideArgs A, int cell, doubl
     for (int k = 0; k < n; ++k) {
       const int pk = A.order[s0 + k];
       const Rec<RT> rk = make_rec<RT>(A.P, g, A.m[pk], A.M[pk], scale);
-      RT dv;
-      const RT Kx = pair_kernel(pc, ri, rk, dv);
-      const RT x = swarm_rate(pc, ri, rk, Kx);
+      RT dv, x, y;
+      PairEval<RT, FAST>::run(pc, ri, rk, dv, x, y);
       acc += x;
       r_out[(int64_t)i * ld + k] = (double)x / scale;
     }
@@ -592,10 +623,10 @@ static hipError_t prepare(Kern kern, size_t lds) {
   return hipSuccess;
 }
 
-template <typename RT, int KMAX>
+template <typename RT, int KMAX, bool FAST>
 static hipError_t run_batched(const CollideArgs &a, int grid_override, hipStream_t s) {
   const size_t lds = std::max(region_bytes<RT>(a.big_cap, 4), 4 * region_bytes<RT>(a.small_cap, 1));
-  auto kern = collide_batched<RT, KMAX>;
+  auto kern = collide_batched<RT, KMAX, FAST>;
   hipError_t e = prepare(kern, lds);
   int dev = 0, cus = 0, per_cu = 0;
   if (e == hipSuccess) e = hipGetDevice(&dev);
@@ -612,37 +643,55 @@ static hipError_t run_batched(const CollideArgs &a, int grid_override, hipStream
   return hipGetLastError();
 }
 
-template <typename RT, int KMAX>
+template <typename RT, int KMAX, bool FAST>
 static hipError_t run_plain(const CollideArgs &a, int n_cells, hipStream_t s) {
   const size_t lds = region_bytes<RT>(a.big_cap, 4);
-  auto kern = collide_plain<RT, KMAX>;
+  auto kern = collide_plain<RT, KMAX, FAST>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
   if (n_cells > 0) kern<<<n_cells, 256, lds, s>>>(a);
   return hipGetLastError();
 }
 
+// the FP32 fast pair path applies to the physical kernel with all five
+// velocity sources (the benchmark disk); everything else takes the generic one
+static bool fast_path(const CollideArgs &a, int precision) {
+  const uint32_t all = DV_BROWNIAN | DV_TURB | DV_RADIAL | DV_AZIMUTHAL | DV_SETTLING;
+  return precision != 0 && a.P.kernel == K_PHYSICAL && (a.P.flags & all) == all;
+}
+
 hipError_t launch_collide(const CollideArgs &a, int precision, int schedule, int n_cells,
                           int max_cell, int grid_override, hipStream_t s) {
   const bool wide = max_cell > 1024;
+  const bool fast = fast_path(a, precision);
   if (schedule == 0) {
     if (precision == 0)
-      return wide ? run_plain<double, 8>(a, n_cells, s) : run_plain<double, 4>(a, n_cells, s);
-    return wide ? run_plain<float, 8>(a, n_cells, s) : run_plain<float, 4>(a, n_cells, s);
+      return wide ? run_plain<double, 8, false>(a, n_cells, s)
+                  : run_plain<double, 4, false>(a, n_cells, s);
+    if (fast)
+      return wide ? run_plain<float, 8, true>(a, n_cells, s)
+                  : run_plain<float, 4, true>(a, n_cells, s);
+    return wide ? run_plain<float, 8, false>(a, n_cells, s)
+                : run_plain<float, 4, false>(a, n_cells, s);
   }
   if (precision == 0)
-    return wide ? run_batched<double, 8>(a, grid_override, s)
-                : run_batched<double, 4>(a, grid_override, s);
-  return wide ? run_batched<float, 8>(a, grid_override, s)
-              : run_batched<float, 4>(a, grid_override, s);
+    return wide ? run_batched<double, 8, false>(a, grid_override, s)
+                : run_batched<double, 4, false>(a, grid_override, s);
+  if (fast)
+    return wide ? run_batched<float, 8, true>(a, grid_override, s)
+                : run_batched<float, 4, true>(a, grid_override, s);
+  return wide ? run_batched<float, 8, false>(a, grid_override, s)
+              : run_batched<float, 4, false>(a, grid_override, s);
 }
 
 hipError_t launch_rates_cell(const CollideArgs &a, int precision, int cell, double *r_out,
                              int64_t ld, double *rowsum_out, hipStream_t s) {
   if (precision == 0)
-    rates_cell<double><<<1, 256, 0, s>>>(a, cell, r_out, ld, rowsum_out);
+    rates_cell<double, false><<<1, 256, 0, s>>>(a, cell, r_out, ld, rowsum_out);
+  else if (fast_path(a, precision))
+    rates_cell<float, true><<<1, 256, 0, s>>>(a, cell, r_out, ld, rowsum_out);
   else
-    rates_cell<float><<<1, 256, 0, s>>>(a, cell, r_out, ld, rowsum_out);
+    rates_cell<float, false><<<1, 256, 0, s>>>(a, cell, r_out, ld, rowsum_out);
   return hipGetLastError();
 }
 

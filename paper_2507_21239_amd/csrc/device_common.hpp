@@ -33,10 +33,11 @@ __host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
   return c;
 }
 
-// uniform in (0,1): top 52 bits of the 64-bit word hi:lo plus half a step
+// uniform in (0,1): top 52 bits of the 64-bit word hi:lo plus half a step,
+// ((w >> 12) + 1/2) 2^-52; evaluated as hi 2^-32 + ((lo >> 12) + 1/2) 2^-52,
+// whose terms and sum are exact in FP64 (53 significant bits at most)
 __host__ __device__ inline double u01(uint32_t lo, uint32_t hi) {
-  const uint64_t w = ((uint64_t)hi << 32) | lo;
-  return ((double)(w >> 12) + 0.5) * 0x1p-52;
+  return fma((double)hi, 0x1p-32, ((double)(lo >> 12) + 0.5) * 0x1p-52);
 }
 
 // ---------------------------------------------------------------------------

@@ -66,7 +66,7 @@ struct TeamScratch {
 // LDS bytes of one particle record in rate precision RT
 template <typename RT>
 constexpr size_t rec_bytes() {
-  return 10 * sizeof(RT);
+  return 12 * sizeof(RT);
 }
 
 // LDS bytes of one team region holding `cap` particles (16-byte multiple)

@@ -114,7 +114,16 @@ struct Rec {
   RT vp;   // azimuthal velocity relative to Keplerian
   RT vz;   // settling velocity at the cell height
   RT nd;   // swarm number density M/(m V), times the cell's rate scale
+  RT ist;  // 1 / St
 };
+
+// the FP32 record carries sqrt(pi) a in place of a, so that the collision
+// cross-section pi (a_i + a_j)^2 needs no extra product
+constexpr double kSqrtPi = 1.7724538509055160273;
+template <typename RT>
+__host__ __device__ constexpr double radius_factor() {
+  return sizeof(RT) == 4 ? kSqrtPi : 1.0;
+}
 
 // particle state in FP64 (the precompute is always FP64), rounded to RT
 template <typename RT>
@@ -126,8 +135,9 @@ __host__ __device__ inline Rec<RT> make_rec(const Model &P, const Gas &g, double
   Rec<RT> o;
   o.m = (RT)m;
   o.im = (RT)(1.0 / m);
-  o.a = (RT)a;
+  o.a = (RT)(a * radius_factor<RT>());
   o.St = (RT)St;
+  o.ist = (RT)(1.0 / St);
   o.h = (RT)(St * St / (St + g.St_eta));
   o.q1 = (RT)(1.0 / (1.0 + St));
   o.vr = (RT)(-2.0 * g.eta_vK * St / (1.0 + St * St));
@@ -203,8 +213,9 @@ __device__ inline Rec<float> make_rec_f(const CellF &c, double m, double M) {
   Rec<float> r;
   r.m = mf;
   r.im = __builtin_amdgcn_rcpf(mf);
-  r.a = a;
+  r.a = a * (float)kSqrtPi;
   r.St = St;
+  r.ist = __builtin_amdgcn_rcpf(St);
   r.h = St * St * __builtin_amdgcn_rcpf(St + c.Ste);
   r.q1 = q1;
   r.vr = c.m2eta * St * w;
@@ -277,7 +288,52 @@ __device__ inline RT pair_kernel(const PairConst<RT> &c, const Rec<RT> &x, const
   }
   dv = rel_velocity(c, x, y);
   const RT s = x.a + y.a;
+  if (sizeof(RT) == 4) return s * s * dv;  // the FP32 radii carry sqrt(pi)
   return (RT)kPi * s * s * dv;
+}
+
+// FP32 rates of a pair for the physical kernel with all five velocity
+// sources: r_xy = n_y K_xy / max(1, dm m_x/m_y) and r_yx, and the relative
+// velocity.  Same quantities as rel_velocity / pair_kernel / swarm_rate,
+// arranged for few instructions: the Ormel & Cuzzi regimes evaluated
+// branch-free from eps = St2/St1 with one shared reciprocal of
+// (1 + eps)(y_a + eps) -- (St1 - St2)/(St1 + St2) = (1 - eps)/(1 + eps) and
+// 2/(1 + eps) (1/(1 + y_a) + eps^3/(y_a + eps)) =
+// 2 ((y_a + eps)/(1 + y_a) + eps^3) / ((1 + eps)(y_a + eps)) --, fused
+// multiply-adds for the quadrature sum, sqrt(pi) folded into the radii.
+__device__ inline void pair_rates_all(const PairConst<float> &c, const Rec<float> &x,
+                                      const Rec<float> &y, float &dv, float &rxy, float &ryx) {
+  constexpr float ya = (float)kYa;
+  constexpr float c1 = (float)(1.0 / (1.0 + kYa));
+  constexpr float b0 = (float)(2.0 * kYa - 1.0);
+  float dv2 = c.cBM * (x.im + y.im);
+  const bool xb = x.St > y.St;
+  const float St1 = xb ? x.St : y.St;
+  const float ist1 = xb ? x.ist : y.ist;
+  const float hd = xb ? x.h - y.h : y.h - x.h;
+  const float eps = (xb ? y.St : x.St) * ist1;
+  const float ye = ya + eps;
+  const float rd = __builtin_amdgcn_rcpf((1.0f + eps) * ye);
+  const float tiny = (1.0f - eps) * (ye * rd) * hd;
+  const float inter = St1 * (b0 - eps + 2.0f * rd * fmaf(ye, c1, eps * eps * eps));
+  const float heavy = x.q1 + y.q1;
+  const float turb = St1 < c.St_eta ? tiny : (St1 < 1.0f ? inter : heavy);
+  dv2 = fmaf(c.Vg2, turb, dv2);
+  float d = x.vr - y.vr;
+  dv2 = fmaf(d, d, dv2);
+  d = x.vp - y.vp;
+  dv2 = fmaf(d, d, dv2);
+  d = x.vz - y.vz;
+  dv2 = fmaf(d, d, dv2);
+  dv = __builtin_amdgcn_sqrtf(dv2);
+  const float s = x.a + y.a;
+  const float K = s * s * dv;
+  rxy = y.nd * K;
+  ryx = x.nd * K;
+  if (c.dm_max > 0.0f) {
+    rxy *= fminf(1.0f, y.m * (x.im * c.inv_dm));
+    ryx *= fminf(1.0f, x.m * (y.im * c.inv_dm));
+  }
 }
 
 // rate of representative particle x against swarm y given K_xy:
