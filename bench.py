@@ -14,6 +14,15 @@ batched form.  Adds the roofline of the collision kernel (vector-ALU bound),
 the FP64 CPU oracle timed on a bounded sample of the same workload, and the
 errors of the GPU forms against the oracle.
 
+`full_step` times the whole path -- adaptive binning, collisions, transport --
+on the large 2-D disk: 2e6 particles, 1000 x 10 equal-count cells of 200,
+8 composition fractions, 1 yr per step with time-limited event loops, mixed
+precision, graph-replayed steps; the binning alone is timed eagerly beside it.
+
+`--copy-calibration` only runs an elementwise copy of 2^28 floats (1 GiB read,
+1 GiB written) and exits: under `rocprofv3 --pmc FETCH_SIZE` / `WRITE_SIZE`
+it gives the factor between those counters and true HBM bytes.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 from __future__ import annotations
@@ -73,6 +82,58 @@ def run_mode(work, precision, schedule, steps, warmup):
     kernel_ms = sum(a.elapsed_time(b) for a, b in marks) / steps
     return dict(wall_s=wall, ms_per_step=wall / steps * 1e3, kernel_ms=kernel_ms,
                 events=st["events"] - ev0)
+
+
+def full_step(steps, warmup):
+    """Whole path on the large 2-D disk: bin -> collide -> transport per step."""
+    import torch
+    from paper_2507_21239_amd import api
+    from paper_2507_21239_amd import workloads as W
+    work = W.c5_large_disk(seed=0)
+    dev = api.to_device(work["particles"])
+    sim = api.Simulation(work["params"], dev, precision="mixed", schedule="batched")
+    stream = torch.cuda.current_stream()
+    sim.bin()
+    for _ in range(warmup):
+        sim.step(W.YR, 0, 1)
+    torch.cuda.synchronize()
+    # binning alone, eager, on the state the timed steps start from
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        sim.bin()
+    b.record(stream)
+    torch.cuda.synchronize()
+    bin_ms = a.elapsed_time(b) / steps
+    ev0 = sim.stats()["events"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a.record(stream)
+    sim.step(W.YR, 0, steps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = sim.stats()
+    sim.close()
+    events = st["events"] - ev0
+    n = len(work["particles"]["m"])
+    return {"workload": "2-D disk 1-100 AU: 2e6 particles, 1000 x 10 equal-count cells of 200, "
+                        "8 composition fractions, drift + settling + mixing + coagulation, "
+                        "1 yr per step, time-limited events",
+            "precision": "mixed", "schedule": "batched", "steps": steps, "warmup": warmup,
+            "particles": n, "active": int(st["n_active"]),
+            "ms_per_step": wall / steps * 1e3, "gpu_ms_per_step": a.elapsed_time(b) / steps,
+            "events_per_step": events / steps, "collisions_per_s": events / wall,
+            "bin_ms": bin_ms}
+
+
+def copy_calibration():
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    log("copy calibration: 1 elementwise kernel, 1073741824 B read, 1073741824 B written")
 
 
 def error_report(work, n_sample=8):
@@ -191,6 +252,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-error", action="store_true", help="skip the error report")
     ap.add_argument("--modes", default="all", help="all | headline")
+    ap.add_argument("--no-full-step", action="store_true", help="skip the full-path measurement")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the HBM counter calibration copy")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the collision step has no multi-GPU path in this "
@@ -203,6 +267,9 @@ def main():
     from paper_2507_21239_amd import workloads as W
 
     assert torch.cuda.is_available(), "no GPU"
+    if args.copy_calibration:
+        copy_calibration()
+        return
     work = W.c4_batched(seed=0, events=EVENTS_PER_CELL)
     counts = np.diff(work["cells"]["cell_start"])
     evals = pair_evals(counts, EVENTS_PER_CELL)
@@ -248,6 +315,11 @@ def main():
     }
     if "fp64_plain" in res:
         out["speedup_mixed_batched_vs_fp64_plain"] = head["collisions_per_s"] / res["fp64_plain"]["collisions_per_s"]
+    if not args.no_full_step:
+        log("full step on the large disk")
+        out["full_step"] = full_step(args.steps, args.warmup)
+        log("full step", f"{out['full_step']['ms_per_step']:.3f} ms/step",
+            f"bin {out['full_step']['bin_ms']:.3f} ms")
     if not args.no_error:
         log("error report")
         out["error"] = error_report(work)

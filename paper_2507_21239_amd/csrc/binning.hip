@@ -3,15 +3,22 @@
 //
 // Radial zones: active particles ranked by (r, index), zone k holds ranks
 // [floor(k Na / n_r), floor((k+1) Na / n_r)).  Cells: inside a zone, ranked
-// by (z, index) and split the same way into n_z cells.  The ranking is a
-// stable least-significant-digit radix sort written for wave64: 8-bit
-// digits, a tile of 2048 keys per 256-thread workgroup, per-tile digit
-// histograms, a scan over tiles per digit, and a stable scatter in which a
-// lane finds the earlier lanes of its wave holding the same digit with eight
-// ballots.  Keys are the IEEE bit patterns of the non-negative coordinates
-// (order-preserving); inactive particles carry the largest key and sort
-// last.  Three sorts per binning: r (8 passes), z (8 passes), then the zone
-// index (1-2 passes), each stable, so ties fall back to the particle index.
+// by (z, index) and split the same way into n_z cells.
+//
+// Rank by r: one reduction gives the active count and the range of the IEEE
+// bit patterns of r (non-negative doubles order like their bits); a 32-bit
+// key (bits - min) >> shift, with shift chosen so keys keep 31 bits, is
+// sorted by a stable least-significant-digit radix sort (8-bit digits, tiles
+// of 2048 keys per 256-thread workgroup, per-tile digit histograms, a scan
+// over tiles per digit, and a scatter that first orders the tile by digit in
+// LDS and then writes each digit's run contiguously).  Stability keeps equal
+// keys in index order; a fix-up pass then orders each run of equal keys by
+// the full 64-bit pattern and index, so the result is the exact (r, index)
+// order.  Rank by z: each zone is a contiguous range of the r order; one
+// workgroup loads its members' (z bits, index) pairs and sorts them with a
+// bitonic network held in registers.  Zones larger than that sort takes
+// (8192) go the global path: 64-bit radix sort by z, then a stable radix pass
+// by zone.
 #include <algorithm>
 
 #include "device_common.hpp"
@@ -31,6 +38,94 @@ __device__ inline uint64_t key_bits(double x) {
   return (uint64_t)__double_as_longlong(x + 0.0);  // -0 -> +0
 }
 
+// ---------------------------------------------------------------------------
+// active count and range of the r bit patterns
+// ---------------------------------------------------------------------------
+// per-workgroup partials {min, max, count}, then one workgroup combines them
+// (no atomics: a few thousand 64-bit atomics on one address serialise)
+__device__ inline void minmax_wave(uint64_t &lo, uint64_t &hi, uint64_t &cnt) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t l2 = __shfl_xor(lo, off, 64), h2 = __shfl_xor(hi, off, 64);
+    lo = l2 < lo ? l2 : lo;
+    hi = h2 > hi ? h2 : hi;
+    cnt += __shfl_xor(cnt, off, 64);
+  }
+}
+
+__device__ inline void minmax_block(uint64_t &lo, uint64_t &hi, uint64_t &cnt) {
+  __shared__ uint64_t s[3][16];
+  minmax_wave(lo, hi, cnt);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s[0][w] = lo;
+    s[1][w] = hi;
+    s[2][w] = cnt;
+  }
+  __syncthreads();
+  lo = ~0ull;
+  hi = 0ull;
+  cnt = 0ull;
+  for (int k = 0; k < nw; ++k) {
+    lo = s[0][k] < lo ? s[0][k] : lo;
+    hi = s[1][k] > hi ? s[1][k] : hi;
+    cnt += s[2][k];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_minmax_part(const double *__restrict__ r,
+                                                     const uint8_t *__restrict__ active,
+                                                     int64_t N, uint64_t *part) {
+  uint64_t lo = ~0ull, hi = 0ull, cnt = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (active[i]) {
+      const uint64_t b = key_bits(r[i]);
+      lo = b < lo ? b : lo;
+      hi = b > hi ? b : hi;
+      ++cnt;
+    }
+  }
+  minmax_block(lo, hi, cnt);
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x] = lo;
+    part[3 * blockIdx.x + 1] = hi;
+    part[3 * blockIdx.x + 2] = cnt;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_minmax_final(const uint64_t *part, int n_part,
+                                                       BinState *bs, DevState *st) {
+  uint64_t lo = ~0ull, hi = 0ull, cnt = 0;
+  for (int k = threadIdx.x; k < n_part; k += blockDim.x) {
+    lo = part[3 * k] < lo ? part[3 * k] : lo;
+    hi = part[3 * k + 1] > hi ? part[3 * k + 1] : hi;
+    cnt += part[3 * k + 2];
+  }
+  minmax_block(lo, hi, cnt);
+  if (threadIdx.x == 0) {
+    bs->min_bits = lo;
+    bs->max_bits = hi;
+    bs->count = (uint32_t)cnt;
+    st->n_active = (int32_t)cnt;
+  }
+}
+
+__device__ inline int key_shift(const BinState *bs) {
+  const uint64_t span = bs->max_bits - bs->min_bits;
+  const int bits = span ? 64 - __builtin_clzll(span) : 0;
+  return bits > 31 ? bits - 31 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_keys_r32(const double *__restrict__ r,
+                                                 const uint8_t *__restrict__ active, int64_t N,
+                                                 const BinState *bs, uint32_t *keys, int32_t *vals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int sh = key_shift(bs);
+  keys[i] = active[i] ? (uint32_t)((key_bits(r[i]) - bs->min_bits) >> sh) : 0xFFFFFFFFu;
+  vals[i] = (int32_t)i;
+}
+
 __global__ __launch_bounds__(256) void k_keys_from_double(const double *__restrict__ x,
                                                           const uint8_t *__restrict__ active,
                                                           int64_t N, uint64_t *keys, int32_t *vals) {
@@ -40,7 +135,11 @@ __global__ __launch_bounds__(256) void k_keys_from_double(const double *__restri
   vals[i] = (int32_t)i;
 }
 
-__global__ __launch_bounds__(256) void k_radix_hist(const uint64_t *__restrict__ keys, int64_t N,
+// ---------------------------------------------------------------------------
+// stable LSD radix pass, 8-bit digits
+// ---------------------------------------------------------------------------
+template <typename KeyT>
+__global__ __launch_bounds__(256) void k_radix_hist(const KeyT *__restrict__ keys, int64_t N,
                                                     int shift, uint32_t *hist, int tiles) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
@@ -93,35 +192,61 @@ __global__ __launch_bounds__(256) void k_radix_scan_rows(uint32_t *hist, int til
   if (threadIdx.x == 255) digit_tot[blockIdx.x] = inc;
 }
 
-__global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *__restrict__ kin,
+// Stable scatter of one tile.  Element order within the tile is (item, wave,
+// lane); a lane finds the earlier lanes of its wave with the same digit by
+// eight ballots, waves and items are chained through per-digit counters.
+// The tile is first written to LDS in digit order, then each digit's run is
+// copied to its global range, so consecutive lanes write consecutive words.
+template <typename KeyT>
+__global__ __launch_bounds__(256) void k_radix_scatter(const KeyT *__restrict__ kin,
                                                        const int32_t *__restrict__ vin,
-                                                       uint64_t *__restrict__ kout,
+                                                       KeyT *__restrict__ kout,
                                                        int32_t *__restrict__ vout, int64_t N,
                                                        int shift, const uint32_t *hist,
                                                        const uint32_t *digit_tot, int tiles) {
-  __shared__ uint32_t base_d[256];
+  __shared__ KeyT sk[kRadixTile];
+  __shared__ int32_t sv[kRadixTile];
+  __shared__ uint32_t gbase[256];   // global position of the tile's first element of digit d
+  __shared__ uint32_t lstart[256];  // position of digit d in the tile's digit order
+  __shared__ uint32_t run_d[256];
   __shared__ uint32_t wcnt[4][256];
   __shared__ uint32_t s[256];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  {
-    const uint32_t v = digit_tot[tid];
-    const uint32_t inc = block_incl_scan_u32(v, s);
-    base_d[tid] = (inc - v) + hist[(size_t)tid * tiles + blockIdx.x];
+  const int64_t tbase = (int64_t)blockIdx.x * kRadixTile;
+  const int tile_n = (int)std::min<int64_t>(kRadixTile, N - tbase);
+
+  KeyT key[kRadixItems];
+  int32_t val[kRadixItems];
+  run_d[tid] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kRadixItems; ++it) {
+    const int li = it * kRadixThreads + tid;
+    key[it] = li < tile_n ? kin[tbase + li] : (KeyT)0;
+    val[it] = li < tile_n ? vin[tbase + li] : 0;
+    if (li < tile_n) atomicAdd(&run_d[(uint32_t)(key[it] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  const int64_t tbase = (int64_t)blockIdx.x * kRadixTile;
+  {
+    const uint32_t cnt = run_d[tid];
+    const uint32_t inc = block_incl_scan_u32(cnt, s);
+    lstart[tid] = inc - cnt;
+    const uint32_t v = digit_tot[tid];
+    const uint32_t ginc = block_incl_scan_u32(v, s);
+    gbase[tid] = (ginc - v) + hist[(size_t)tid * tiles + blockIdx.x];
+    run_d[tid] = inc - cnt;  // running local position of digit d
+  }
+  __syncthreads();
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   for (int it = 0; it < kRadixItems; ++it) {
-    const int64_t i = tbase + it * kRadixThreads + tid;
-    const bool valid = i < N;
-    const uint64_t key = valid ? kin[i] : 0ull;
-    const int32_t val = valid ? vin[i] : 0;
-    const uint32_t digit = (uint32_t)(key >> shift) & 255u;
-    uint64_t same = __ballot(valid);
+    const int li = it * kRadixThreads + tid;
+    const bool valid = li < tile_n;
+    const uint32_t digit = (uint32_t)(key[it] >> shift) & 255u;
+    uint64_t same = ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
       const bool bit = (digit >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
+      const uint64_t bb = ballot(bit);
       same &= bit ? bb : ~bb;
     }
     const uint32_t rank = (uint32_t)__popcll(same & lt_mask);
@@ -131,32 +256,96 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *__restric
     if (valid && rank == 0) wcnt[wave][digit] = (uint32_t)__popcll(same);
     __syncthreads();
     {
-      uint32_t run = base_d[tid];
+      uint32_t run = run_d[tid];
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
         const uint32_t c = wcnt[w][tid];
         wcnt[w][tid] = run;
         run += c;
       }
-      base_d[tid] = run;
+      run_d[tid] = run;
     }
     __syncthreads();
     if (valid) {
       const uint32_t pos = wcnt[wave][digit] + rank;
-      kout[pos] = key;
-      vout[pos] = val;
+      sk[pos] = key[it];
+      sv[pos] = val[it];
     }
     __syncthreads();
   }
+  for (int p = tid; p < tile_n; p += kRadixThreads) {
+    const KeyT k = sk[p];
+    const uint32_t d = (uint32_t)(k >> shift) & 255u;
+    const uint32_t g = gbase[d] + (uint32_t)p - lstart[d];
+    kout[g] = k;
+    vout[g] = sv[p];
+  }
 }
 
-__global__ __launch_bounds__(256) void k_count_active(const uint64_t *__restrict__ keys, int64_t N,
-                                                      DevState *st) {
+template <typename KeyT>
+static hipError_t radix_pass(KeyT *const keys[2], int32_t *const vals[2], uint32_t *hist,
+                             uint32_t *digit_tot, int &cur, int64_t N, int shift, hipStream_t s) {
+  const int tiles = radix_tiles(N);
+  k_radix_hist<KeyT><<<tiles, kRadixThreads, 0, s>>>(keys[cur], N, shift, hist, tiles);
+  k_radix_scan_rows<<<256, 256, 0, s>>>(hist, tiles, digit_tot);
+  k_radix_scatter<KeyT><<<tiles, kRadixThreads, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1],
+                                                        vals[cur ^ 1], N, shift, hist, digit_tot,
+                                                        tiles);
+  cur ^= 1;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// exact order inside runs of equal 32-bit keys: by full r bits, then index.
+// Stability leaves every run in index order, so a run needs work only if two
+// neighbours in it differ in r.  The first kernel copies the order out and
+// flags such neighbours; the second lets the first flagged position of each
+// run (flags and keys are read-only there) insertion-sort the run by
+// (bits of r, index).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ties_copy(const uint32_t *__restrict__ keys,
+                                                   const int32_t *__restrict__ vals,
+                                                   const double *__restrict__ r, int64_t N,
+                                                   const DevState *st, int32_t *__restrict__ by_r,
+                                                   uint8_t *__restrict__ flag) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= N) return;
-  const bool act = keys[p] != ~0ull;
-  if (act && (p + 1 == N || keys[p + 1] == ~0ull)) st->n_active = (int32_t)(p + 1);
-  if (p == 0 && !act) st->n_active = 0;
+  const int32_t v = vals[p];
+  by_r[p] = v;
+  uint8_t f = 0;
+  if (p + 1 < (int64_t)st->n_active && keys[p + 1] == keys[p])
+    f = key_bits(r[v]) != key_bits(r[vals[p + 1]]) ? 1 : 0;
+  flag[p] = f;
+}
+
+__global__ __launch_bounds__(256) void k_fix_ties(const uint32_t *__restrict__ keys,
+                                                  const uint8_t *__restrict__ flag,
+                                                  const double *__restrict__ r, int64_t N,
+                                                  const DevState *st, int32_t *by_r) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N || !flag[p]) return;
+  const int64_t na = st->n_active;
+  const uint32_t k = keys[p];
+  int64_t s = p;
+  while (s > 0 && keys[s - 1] == k) {
+    if (flag[s - 1]) return;  // an earlier position of this run does the work
+    --s;
+  }
+  int64_t e = p + 2;
+  while (e < na && keys[e] == k) ++e;
+  for (int64_t a = s + 1; a < e; ++a) {
+    const int32_t v = by_r[a];
+    const uint64_t bv = key_bits(r[v]);
+    int64_t b = a - 1;
+    while (b >= s) {
+      const int32_t u = by_r[b];
+      const uint64_t bu = key_bits(r[u]);
+      if (bu < bv || (bu == bv && u < v)) break;
+      by_r[b + 1] = u;
+      --b;
+    }
+    by_r[b + 1] = v;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_copy_i32(const int32_t *__restrict__ a,
@@ -179,6 +368,155 @@ __global__ __launch_bounds__(256) void k_keys_zone(const int32_t *__restrict__ v
                                                    uint64_t *keys) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < N) keys[i] = (uint64_t)(uint32_t)zone[vals[i]];
+}
+
+// ---------------------------------------------------------------------------
+// order of each zone by (z, index): one workgroup per zone runs a bitonic
+// network over the zone padded to P = 8 x threads (a power of two, >= 512).
+// Thread t keeps positions 8t .. 8t+7 in registers: strides below 8 compare
+// inside a thread, strides 8 .. 256 pair lanes of one wave (shuffles, no
+// barrier), strides of 512 and up exchange through LDS between barriers.
+// ---------------------------------------------------------------------------
+constexpr int kZoneItems = 8;
+
+__device__ inline bool pair_gt(uint64_t ka, int32_t ia, uint64_t kb, int32_t ib) {
+  return ka > kb || (ka == kb && ia > ib);
+}
+
+// the element at position p takes the smaller of (own, partner) if it is the
+// lower position of an ascending pair or the upper one of a descending pair
+__device__ inline void keep_one(uint64_t &k, int32_t &i, uint64_t k2, int32_t i2, int p,
+                                int stride, int size) {
+  const bool want_min = ((p & stride) == 0) == ((p & size) == 0);
+  const bool take = want_min ? pair_gt(k, i, k2, i2) : pair_gt(k2, i2, k, i);
+  k = take ? k2 : k;
+  i = take ? i2 : i;
+}
+
+// value of lane (lane ^ LM) of the wave.  Lane xors below 16 are DPP moves
+// (VALU): quad permutes give xor 1 and xor 2; a half-row mirror (xor 7)
+// followed by a quad reverse (xor 3) gives xor 4; a row mirror (xor 15)
+// followed by a half-row mirror gives xor 8.  Xors 16 and 32 use the LDS
+// permute network.
+template <int LM>
+__device__ inline uint32_t lane_xor(uint32_t v) {
+  const int x = (int)v;
+  if constexpr (LM == 1) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xf, 0xf, true);
+  } else if constexpr (LM == 2) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xf, 0xf, true);
+  } else if constexpr (LM == 4) {
+    const int y = __builtin_amdgcn_update_dpp(0, x, 0x141, 0xf, 0xf, true);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, y, 0x1B, 0xf, 0xf, true);
+  } else if constexpr (LM == 8) {
+    const int y = __builtin_amdgcn_update_dpp(0, x, 0x140, 0xf, 0xf, true);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, y, 0x141, 0xf, 0xf, true);
+  } else {
+    return (uint32_t)__shfl_xor(x, LM, 64);
+  }
+}
+
+// one exchange phase between lanes (strides 8 .. 256): for these strides the
+// bits tested by the pair direction lie above the thread's own 8 positions
+template <int LM>
+__device__ inline void zone_lane_phase(uint64_t (&key)[kZoneItems], int32_t (&idx)[kZoneItems],
+                                       int base, int stride, int size) {
+  const bool want_min = ((base & stride) == 0) == ((base & size) == 0);
+#pragma unroll
+  for (int e = 0; e < kZoneItems; ++e) {
+    const uint32_t lo = lane_xor<LM>((uint32_t)key[e]);
+    const uint32_t hi = lane_xor<LM>((uint32_t)(key[e] >> 32));
+    const uint64_t k2 = ((uint64_t)hi << 32) | lo;
+    const int32_t i2 = (int32_t)lane_xor<LM>((uint32_t)idx[e]);
+    const bool take = want_min ? pair_gt(key[e], idx[e], k2, i2) : pair_gt(k2, i2, key[e], idx[e]);
+    key[e] = take ? k2 : key[e];
+    idx[e] = take ? i2 : idx[e];
+  }
+}
+
+template <int S>
+__device__ inline void zone_reg_phase(uint64_t (&key)[kZoneItems], int32_t (&idx)[kZoneItems],
+                                      int base, int size) {
+#pragma unroll
+  for (int e = 0; e < kZoneItems; ++e) {
+    if (e & S) continue;
+    const bool up = ((base + e) & size) == 0;
+    const bool gt = pair_gt(key[e], idx[e], key[e + S], idx[e + S]);
+    if (gt == up) {
+      const uint64_t tk = key[e];
+      const int32_t ti = idx[e];
+      key[e] = key[e + S];
+      idx[e] = idx[e + S];
+      key[e + S] = tk;
+      idx[e + S] = ti;
+    }
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_zone_sort(const int32_t *__restrict__ by_r,
+                                                    const double *__restrict__ z, int n_r,
+                                                    const DevState *st, int32_t *order) {
+  extern __shared__ __align__(16) char smem[];
+  const int64_t na = st->n_active;
+  const int zk = blockIdx.x;
+  const int64_t b0 = (int64_t)zk * na / n_r, b1 = (int64_t)(zk + 1) * na / n_r;
+  const int nk = (int)(b1 - b0);
+  if (nk <= 0) return;
+  const int P = blockDim.x * kZoneItems;
+  const int tid = threadIdx.x;
+  const int base = tid * kZoneItems;
+  uint64_t key[kZoneItems];
+  int32_t idx[kZoneItems];
+#pragma unroll
+  for (int e = 0; e < kZoneItems; ++e) {
+    const int p = base + e;
+    if (p < nk) {
+      const int32_t v = by_r[b0 + p];
+      idx[e] = v;
+      key[e] = key_bits(z[v]);
+    } else {
+      idx[e] = 0x7FFFFFFF;
+      key[e] = ~0ull;
+    }
+  }
+  uint64_t *lk = (uint64_t *)smem;
+  int32_t *li = (int32_t *)(lk + P);
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride >= 64 * kZoneItems) {
+#pragma unroll
+        for (int e = 0; e < kZoneItems; ++e) {
+          lk[base + e] = key[e];
+          li[base + e] = idx[e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < kZoneItems; ++e) {
+          const int q = (base + e) ^ stride;
+          keep_one(key[e], idx[e], lk[q], li[q], base + e, stride, size);
+        }
+        __syncthreads();
+      } else if (stride >= kZoneItems) {
+        switch (stride / kZoneItems) {
+          case 1: zone_lane_phase<1>(key, idx, base, stride, size); break;
+          case 2: zone_lane_phase<2>(key, idx, base, stride, size); break;
+          case 4: zone_lane_phase<4>(key, idx, base, stride, size); break;
+          case 8: zone_lane_phase<8>(key, idx, base, stride, size); break;
+          case 16: zone_lane_phase<16>(key, idx, base, stride, size); break;
+          default: zone_lane_phase<32>(key, idx, base, stride, size); break;
+        }
+      } else if (stride == 4) {
+        zone_reg_phase<4>(key, idx, base, size);
+      } else if (stride == 2) {
+        zone_reg_phase<2>(key, idx, base, size);
+      } else {
+        zone_reg_phase<1>(key, idx, base, size);
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < kZoneItems; ++e)
+    if (base + e < nk) order[b0 + base + e] = idx[e];
 }
 
 // member ranges, edges, volumes and gas primaries of every cell
@@ -232,15 +570,11 @@ __global__ __launch_bounds__(256) void k_cells(Model P, int n_r, int n_z,
   }
 }
 
-static hipError_t radix_pass(BinBuffers &b, int &cur, int64_t N, int shift, hipStream_t s) {
-  const int tiles = radix_tiles(N);
-  k_radix_hist<<<tiles, kRadixThreads, 0, s>>>(b.keys[cur], N, shift, b.hist, tiles);
-  k_radix_scan_rows<<<256, 256, 0, s>>>(b.hist, tiles, b.digit_tot);
-  k_radix_scatter<<<tiles, kRadixThreads, 0, s>>>(b.keys[cur], b.vals[cur], b.keys[cur ^ 1],
-                                                  b.vals[cur ^ 1], N, shift, b.hist, b.digit_tot,
-                                                  tiles);
-  cur ^= 1;
-  return hipGetLastError();
+// padded size of the zone sort: a power of two, at least 512 (one full wave)
+int zone_sort_size(int64_t zone_max) {
+  int P = 64 * kZoneItems;
+  while (P < zone_max) P <<= 1;
+  return P;
 }
 
 hipError_t launch_binning(const Model &P, int n_r, int n_z, const double *r, const double *z,
@@ -250,25 +584,43 @@ hipError_t launch_binning(const Model &P, int n_r, int n_z, const double *r, con
   if (N <= 0 || N > b.cap) return hipErrorInvalidValue;
   const unsigned g1 = (unsigned)((N + 255) / 256);
   hipError_t e;
-  int cur = 0;
   // 1. rank by (r, index)
-  k_keys_from_double<<<g1, 256, 0, s>>>(r, active, N, b.keys[0], b.vals[0]);
-  for (int sh = 0; sh < 64; sh += 8)
-    if ((e = radix_pass(b, cur, N, sh, s)) != hipSuccess) return e;
-  k_count_active<<<g1, 256, 0, s>>>(b.keys[cur], N, state);
-  k_copy_i32<<<g1, 256, 0, s>>>(b.vals[cur], b.by_r, N);
-  k_zone<<<g1, 256, 0, s>>>(b.by_r, N, n_r, state, b.zone);
-  // 2. rank by (zone, z, index): z first, then a stable pass over the zone
-  cur = 0;
-  k_keys_from_double<<<g1, 256, 0, s>>>(z, active, N, b.keys[0], b.vals[0]);
-  for (int sh = 0; sh < 64; sh += 8)
-    if ((e = radix_pass(b, cur, N, sh, s)) != hipSuccess) return e;
-  if (n_r > 1) {
-    k_keys_zone<<<g1, 256, 0, s>>>(b.vals[cur], b.zone, N, b.keys[cur]);
-    for (int sh = 0; sh < 16 && (n_r >> sh) > 0; sh += 8)
-      if ((e = radix_pass(b, cur, N, sh, s)) != hipSuccess) return e;
+  const unsigned n_part = std::min<unsigned>(g1, kMinmaxParts);
+  k_minmax_part<<<n_part, 256, 0, s>>>(r, active, N, b.part);
+  k_minmax_final<<<1, 1024, 0, s>>>(b.part, (int)n_part, b.bs, state);
+  k_keys_r32<<<g1, 256, 0, s>>>(r, active, N, b.bs, b.k32[0], b.vals[0]);
+  int cur = 0;
+  for (int sh = 0; sh < 32; sh += 8)
+    if ((e = radix_pass<uint32_t>(b.k32, b.vals, b.hist, b.digit_tot, cur, N, sh, s)) != hipSuccess)
+      return e;
+  k_ties_copy<<<g1, 256, 0, s>>>(b.k32[cur], b.vals[cur], r, N, state, b.by_r, b.flag);
+  k_fix_ties<<<g1, 256, 0, s>>>(b.k32[cur], b.flag, r, N, state, b.by_r);
+  // 2. rank by (z, index) inside each zone
+  const int64_t zone_max = (N + n_r - 1) / n_r;  // no zone holds more
+  if (zone_max <= kZoneSortMax) {
+    const int Pz = zone_sort_size(zone_max);
+    const size_t lds = Pz > 64 * kZoneItems ? (size_t)Pz * (sizeof(uint64_t) + sizeof(int32_t)) : 0;
+    if (lds > 64 * 1024) {
+      e = hipFuncSetAttribute((const void *)k_zone_sort, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    k_zone_sort<<<n_r, Pz / kZoneItems, lds, s>>>(b.by_r, z, n_r, state, order);
+  } else {
+    k_zone<<<g1, 256, 0, s>>>(b.by_r, N, n_r, state, b.zone);
+    cur = 0;
+    k_keys_from_double<<<g1, 256, 0, s>>>(z, active, N, b.keys[0], b.vals[0]);
+    for (int sh = 0; sh < 64; sh += 8)
+      if ((e = radix_pass<uint64_t>(b.keys, b.vals, b.hist, b.digit_tot, cur, N, sh, s)) != hipSuccess)
+        return e;
+    if (n_r > 1) {
+      k_keys_zone<<<g1, 256, 0, s>>>(b.vals[cur], b.zone, N, b.keys[cur]);
+      for (int sh = 0; sh < 16 && (n_r >> sh) > 0; sh += 8)
+        if ((e = radix_pass<uint64_t>(b.keys, b.vals, b.hist, b.digit_tot, cur, N, sh, s)) != hipSuccess)
+          return e;
+    }
+    k_copy_i32<<<g1, 256, 0, s>>>(b.vals[cur], order, N);
   }
-  k_copy_i32<<<g1, 256, 0, s>>>(b.vals[cur], order, N);
   // 3. cells
   const int nc = n_r * n_z;
   k_cells<<<(nc + 255) / 256, 256, 0, s>>>(P, n_r, n_z, r, z, b.by_r, order, state, cell_start,

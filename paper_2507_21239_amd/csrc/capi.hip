@@ -169,12 +169,23 @@ mcd_status alloc_grid(mcd_ctx *c, int32_t n_cells, int64_t n_order) {
   return MCD_OK;
 }
 
+void free_binning(BinBuffers &b) {
+  void *const all[] = {b.keys[0], b.keys[1], b.k32[0], b.k32[1], b.vals[0], b.vals[1], b.flag,
+                       b.bs,      b.part,    b.by_r,   b.zone,   b.hist,   b.digit_tot};
+  for (void *p : all) dfree(p);
+  b = BinBuffers{};
+}
+
 mcd_status alloc_binning(mcd_ctx *c, int64_t N) {
   if (c->bb.cap >= N) return MCD_OK;
   BinBuffers &b = c->bb;
+  free_binning(b);
   const int tiles = radix_tiles(N);
   if (dalloc(&b.keys[0], N) != hipSuccess || dalloc(&b.keys[1], N) != hipSuccess ||
+      dalloc(&b.k32[0], N) != hipSuccess || dalloc(&b.k32[1], N) != hipSuccess ||
       dalloc(&b.vals[0], N) != hipSuccess || dalloc(&b.vals[1], N) != hipSuccess ||
+      dalloc(&b.flag, N) != hipSuccess || dalloc(&b.bs, 1) != hipSuccess ||
+      dalloc(&b.part, (size_t)3 * kMinmaxParts) != hipSuccess ||
       dalloc(&b.by_r, N) != hipSuccess || dalloc(&b.zone, N) != hipSuccess ||
       dalloc(&b.hist, (size_t)256 * tiles) != hipSuccess ||
       dalloc(&b.digit_tot, 256) != hipSuccess)
@@ -312,6 +323,13 @@ mcd_status mcd_init(const mcd_params *params, const mcd_particles *particles, vo
 
 mcd_status mcd_bin(mcd_ctx *c, const mcd_cells *cells) {
   if (!c) return MCD_EINVAL;
+  if (!cells && c->adaptive && c->have_cells) {
+    // re-binning on the same grid: the cell lists, buffers and any captured
+    // step graph stay valid; only the binning kernels are enqueued
+    mcd_status st;
+    if ((st = enqueue_bin(c, c->stream)) != MCD_OK) return st;
+    return MCD_OK;
+  }
   drop_graph(c);
   if (!cells) {
     const int64_t N = c->part.n;
@@ -506,14 +524,7 @@ void mcd_free(mcd_ctx *c) {
   drop_graph(c);
   free_grid(c);
   BinBuffers &b = c->bb;
-  dfree(b.keys[0]);
-  dfree(b.keys[1]);
-  dfree(b.vals[0]);
-  dfree(b.vals[1]);
-  dfree(b.by_r);
-  dfree(b.zone);
-  dfree(b.hist);
-  dfree(b.digit_tot);
+  free_binning(b);
   dfree(c->d_state);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;

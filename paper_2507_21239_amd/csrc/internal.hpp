@@ -89,9 +89,26 @@ hipError_t launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t
                          hipStream_t s);
 
 // binning (binning.hip)
+// active count and range of the IEEE bit patterns of r
+struct BinState {
+  uint64_t min_bits, max_bits;
+  uint32_t count, pad;
+};
+
+// zones up to this many members are ordered by z in one workgroup (bitonic
+// network of 1024 threads x 8 elements, 96 KB of LDS); larger zones take the
+// global radix path
+constexpr int kZoneSortMax = 8192;
+// workgroups of the first reduction over r (partials of 3 words each)
+constexpr int kMinmaxParts = 1024;
+
 struct BinBuffers {
-  uint64_t *keys[2];
+  uint64_t *keys[2];   // 64-bit keys of the global z path
+  uint32_t *k32[2];    // 32-bit keys of the r sort
   int32_t *vals[2];
+  uint8_t *flag;       // neighbours with equal r keys but different r
+  BinState *bs;
+  uint64_t *part;      // [3 kMinmaxParts] partial {min, max, count}
   int32_t *by_r;       // active particle indices by ascending (r, index)
   int32_t *zone;       // zone of every particle (n_r for inactive)
   uint32_t *hist;      // radix histogram [256][tiles]

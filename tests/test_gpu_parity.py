@@ -39,19 +39,36 @@ def test_philox_words_bit_exact():
         assert np.array_equal(out[k], O.philox(ctr[k], [key & 0xFFFFFFFF, key >> 32]))
 
 
-@pytest.mark.parametrize("N,n_r,n_z,seed", [(5000, 10, 5, 0), (4000, 1, 20, 1), (2049, 7, 3, 2),
-                                            (100_000, 50, 10, 3), (33, 4, 8, 4)])
-def test_binning_bit_exact(N, n_r, n_z, seed):
+# (N, n_r, n_z, seed, ulp_clusters): zones of up to 8192 members are ordered
+# in LDS (16384 / 2 is that maximum), larger ones (40000 / 3, 30000 / 1) take
+# the global radix path (cells stay small enough for the FP64 step);
+# ulp_clusters puts a fifth of the radii within a few ulps of each other so
+# that the 32-bit r keys tie and the exact fix-up runs
+@pytest.mark.parametrize("N,n_r,n_z,seed,ulp", [
+    (5000, 10, 5, 0, False), (4000, 1, 20, 1, False), (2049, 7, 3, 2, False),
+    (100_000, 50, 10, 3, False), (33, 4, 8, 4, False), (16384, 2, 9, 5, False),
+    (40000, 3, 20, 6, False), (30000, 1, 30, 7, True), (20000, 40, 4, 8, True),
+    (1, 1, 1, 9, False)])
+def test_binning_bit_exact(N, n_r, n_z, seed, ulp):
     api = _api()
     rng = np.random.default_rng(seed)
     p = W.benchmark_params(n_r=n_r, n_z=n_z)
     r = W.AU * 10.0 ** rng.uniform(0, 2, N)
     z = np.abs(rng.standard_normal(N)) * 0.05 * r
     k = rng.choice(N, N // 5, replace=False)
-    r[k[: len(k) // 2]] = r[k[len(k) // 2: 2 * (len(k) // 2)]]
-    z[k[::3]] = z[k[0]]
-    z[k[1::7]] = 0.0
+    if len(k):
+        r[k[: len(k) // 2]] = r[k[len(k) // 2: 2 * (len(k) // 2)]]
+        z[k[::3]] = z[k[0]]
+        z[k[1::7]] = 0.0
+    if ulp:
+        # clusters of 40 around a few centres, offsets of 0..60 ulps, some equal
+        c = rng.choice(N, N // 5, replace=False)
+        centres = W.AU * 10.0 ** rng.uniform(0, 2, len(c) // 40 + 1)
+        base = centres[np.arange(len(c)) // 40]
+        r[c] = base + rng.integers(0, 60, len(c)) * np.spacing(base)
     active = (rng.random(N) > 0.1).astype(np.uint8)
+    if N == 1:
+        active[:] = 1
     part = dict(r=r, z=z, m=np.full(N, 1e-11), M=np.ones(N), active=active)
     say("binning", N, n_r, n_z)
     sim = api.Simulation(p, api.to_device(part), precision="fp64")
