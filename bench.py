@@ -46,6 +46,35 @@ F_PAIR = 39
 PEAK_FP32_TFLOPS = 157.3
 EVENTS_PER_CELL = 1000
 
+# HBM traffic of one launch of the collision kernel on this workload, from
+# `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` runs (KiB per dispatch),
+# scaled by the same counters' reading for an elementwise copy of known size
+# (a 1 GiB read shows as 524288 KiB of FETCH_SIZE, a 1 GiB write as 1048576 KiB
+# of WRITE_SIZE: factors 2.0 and 1.0).
+# Valid only for the kernel sources it was taken on: their SHA-256 is kept
+# and compared at run time; on any change `traffic` is reported as null.
+TRAFFIC = {"fetch_kib": None, "write_kib": None, "fetch_factor": 2.0, "write_factor": 1.0,
+           "sources_sha256": None}
+KERNEL_SOURCES = ("paper_2507_21239_amd/csrc/collide.hip", "paper_2507_21239_amd/csrc/physics.hpp",
+                  "paper_2507_21239_amd/csrc/device_common.hpp", "paper_2507_21239_amd/csrc/internal.hpp")
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_bytes():
+    """Counter-derived HBM bytes per launch, or None if the kernel changed."""
+    t = TRAFFIC
+    if t["fetch_kib"] is None or t["sources_sha256"] != kernel_sources_sha256():
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -251,7 +280,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-error", action="store_true", help="skip the error report")
-    ap.add_argument("--modes", default="all", help="all | headline")
+    ap.add_argument("--modes", default="all",
+                    help="all | headline | none (none: only the full step, for profiling)")
     ap.add_argument("--no-full-step", action="store_true", help="skip the full-path measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the HBM counter calibration copy")
@@ -275,6 +305,11 @@ def main():
     evals = pair_evals(counts, EVENTS_PER_CELL)
     log("workload", len(counts), "cells", int(counts.sum()), "particles", f"{evals:.3e} pair evals/step")
 
+    if args.modes == "none":
+        fs = full_step(args.steps, args.warmup)
+        print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
+                          "full_step": fs}), flush=True)
+        return
     modes = [("mixed", "batched")] if args.modes == "headline" else \
         [("fp64", "plain"), ("fp64", "batched"), ("mixed", "plain"), ("mixed", "batched")]
     res = {}
@@ -309,7 +344,7 @@ def main():
         "forms": {k: {"collisions_per_s": v["collisions_per_s"], "pair_evals_per_s": v["pair_evals_per_s"],
                       "ms_per_step": v["ms_per_step"], "kernel_ms": v["kernel_ms"]} for k, v in res.items()},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_bytes(),
                      "kernel": "collide_batched<float>", "flops_per_pair": F_PAIR,
                      "pair_evals_per_launch": evals},
     }

@@ -11,8 +11,11 @@
 // lane t owns the contiguous slots j = t*K .. t*K+K-1 (K = ceil(n/(64 nw))),
 // so the cumulative rate of j is the team prefix of the lanes' partial sums
 // plus a short in-lane prefix.  Prefix sums are FP64 DPP scans; four-wave
-// teams exchange wave totals through LDS (two barriers per selection, one
-// for the new row sum).  Particle records live in LDS as packed vectors
+// teams exchange wave totals through LDS (one barrier per scan).  A
+// selection is made by the wave whose prefix range holds the target -- every
+// wave finds it from the exchanged totals -- and published with one more
+// barrier.  The uniforms of 64 events are drawn at once, one event per lane.
+// Particle records live in LDS as packed vectors
 // indexed by s = q*64nw + t (slot q of lane t), so a wave reads consecutive
 // 16-byte words.  Row sums (FP64), the per-event row values, masses and
 // particle indices stay in registers of the owning lane; masses go back to
@@ -181,23 +184,29 @@ struct RecAfter<float> {
   }
 };
 
-// Pick the first slot whose cumulative value exceeds target.  v[] are the
-// lane's K values in canonical order, part their sum, incl the team-inclusive
-// prefix of part.  A lane with an empty partial is never chosen (the team
-// prefix is not exactly monotone under rounding); if rounding leaves no
-// prefix above the target, the last nonzero entry is taken.  Returns the
-// chosen slot, its owner and the owner's payloads a0[q], a1[q], a2[q], ai[q]
-// on every lane of the team.
-template <int KMAX, typename VT, typename P2>
-__device__ inline Cand team_pick(Team &tm, double incl, double part, const VT *v, int K,
-                                 double target, const double *a0, const double *a1,
-                                 const P2 *a2, const int *ai) {
-  const bool hit = incl > target && part > 0.0;
-  const uint64_t bh = ballot(hit), bf = ballot(part > 0.0);
-  const int first = first_set(bh);
+// ---------------------------------------------------------------------------
+// selection: the first slot whose cumulative value exceeds a target
+// ---------------------------------------------------------------------------
+// Search inside one wave.  v[] are the lane's K values in canonical order,
+// part their sum, incl the team-inclusive prefix of part.  The chosen lane is
+// the first with incl > target and a nonzero partial (the team prefix is not
+// exactly monotone under rounding), else the wave's last lane with a nonzero
+// partial; inside it, the first slot whose running sum exceeds the target,
+// else its last nonzero slot.  Fills c (team lane, slot, payloads a0[q],
+// a1[q], ai[q], and whether a lane passed the target) uniformly over the
+// wave; false if no lane of the wave has a nonzero partial.
+template <int KMAX, typename VT, typename PT>
+__device__ inline bool wave_pick(int wave, double incl, double part, const VT *v, int K,
+                                 double target, const double *a0, const PT *a1, const int *ai,
+                                 Cand &c) {
+  const bool pos = part > 0.0;
+  const uint64_t bf = ballot(pos);
+  if (bf == 0) return false;
+  const int first = first_set(ballot(pos && incl > target));
   const int src = first >= 0 ? first : last_set(bf);
   // every lane searches its own slots as if it owned the pick (no divergent
-  // code); the owner's answer is read afterwards
+  // code); the owner's slot is read afterwards, then its payloads with a
+  // wave-uniform slot index
   double cum = incl - part;
   int qhit = -1, last = -1;
 #pragma unroll
@@ -208,31 +217,52 @@ __device__ inline Cand team_pick(Team &tm, double incl, double part, const VT *v
       qhit = (qhit < 0 && cum > target) ? q : qhit;
     }
   }
-  const int qsel = (first >= 0 && qhit >= 0) ? qhit : last;
-  double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-  int gi = -1;
+  const int qs = readlane_i((first >= 0 && qhit >= 0) ? qhit : last, src);
+  c.q = qs;
+  c.lane = wave * 64 + src;
+  c.hit = first >= 0 ? 1 : 0;
+  c.p0 = c.p1 = c.p2 = 0.0;
+  c.gi = -1;
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) {
-    const bool m = q == qsel;
-    p0 = m ? a0[q] : p0;
-    p1 = m ? a1[q] : p1;
-    p2 = m ? (double)a2[q] : p2;
-    gi = m ? ai[q] : gi;
+    if (q == qs) {
+      c.p0 = readlane_d(a0[q], src);
+      c.p1 = readlane_d((double)a1[q], src);
+      c.gi = readlane_i(ai[q], src);
+    }
   }
-  Cand o{0.0, 0.0, 0.0, -1, -1, first >= 0 ? 1 : 0, -1};
-  if (src < 0) {
-    if (tm.nw == 1) return o;
-  } else {
-    o.q = readlane_i(qsel, src);
-    o.lane = tm.wave * 64 + src;
-    o.gi = readlane_i(gi, src);
-    o.p0 = readlane_d(p0, src);
-    o.p1 = readlane_d(p1, src);
-    o.p2 = readlane_d(p2, src);
-    if (tm.nw == 1) return o;
+  return true;
+}
+
+// The wave of a multi-wave team that holds the target: the first whose
+// team-inclusive prefix at its last lane exceeds it.  That prefix is rebuilt
+// from the wave totals of the latest exchange with the same FP64 operations
+// the lanes used (offset of the earlier waves, plus the wave's total, plus
+// delta from team lane 64 fix_wave on), so every wave finds the same owner
+// without another exchange.  -1 if no wave's prefix exceeds the target.
+__device__ inline int owner_wave(const Team &tm, double target, int fix_wave, double delta) {
+  double off = 0.0;
+  for (int w = 0; w < tm.nw; ++w) {
+    const double wt = tm.S->tot[tm.phase][w];
+    double cum = off + wt;
+    if (w >= fix_wave) cum += delta;
+    if (cum > target) return w;
+    off += wt;
   }
+  return -1;
+}
+
+// Every wave searches and publishes its candidate; the team takes the first
+// wave with a lane past the target, else the last wave with any nonzero
+// partial.  q < 0: nothing to pick.
+template <int KMAX, typename VT, typename PT>
+__device__ inline Cand pick_all_waves(Team &tm, double incl, double part, const VT *v, int K,
+                                      double target, const double *a0, const PT *a1,
+                                      const int *ai) {
+  Cand h{0.0, 0.0, 0.0, -1, -1, 0, -1};
+  if (!wave_pick<KMAX>(tm.wave, incl, part, v, K, target, a0, a1, ai, h)) h.q = -1;
   tm.phase ^= 1;
-  if (tm.lane == 0) tm.S->cand[tm.phase][tm.wave] = o;
+  if (tm.lane == 0) tm.S->cand[tm.phase][tm.wave] = h;
   block_lds_sync();
   int wsel = -1;
   for (int w = tm.nw - 1; w >= 0; --w) {
@@ -243,11 +273,70 @@ __device__ inline Cand team_pick(Team &tm, double incl, double part, const VT *v
     for (int w = 0; w < tm.nw; ++w)
       if (tm.S->cand[tm.phase][w].q >= 0) wsel = w;
   }
-  if (wsel < 0) {
-    Cand z{0.0, 0.0, 0.0, -1, -1, 0, -1};
-    return z;
-  }
+  if (wsel < 0) return Cand{0.0, 0.0, 0.0, -1, -1, 0, -1};
   return tm.S->cand[tm.phase][wsel];
+}
+
+// Team-wide selection: one wave searches (the owner of the target) and
+// publishes; if rounding leaves no lane of that wave past the target, every
+// wave searches (pick_all_waves).  The same result on every lane of the team.
+template <int KMAX, typename VT, typename PT>
+__device__ inline Cand team_pick(Team &tm, double incl, double part, const VT *v, int K,
+                                 double target, int fix_wave, double delta, const double *a0,
+                                 const PT *a1, const int *ai) {
+  Cand c{0.0, 0.0, 0.0, -1, -1, 0, -1};
+  if (tm.nw == 1) {
+    if (!wave_pick<KMAX>(0, incl, part, v, K, target, a0, a1, ai, c)) c.q = -1;
+    return c;
+  }
+  const int ow = owner_wave(tm, target, fix_wave, delta);
+  tm.phase ^= 1;
+  if (tm.wave == ow) {
+    if (!wave_pick<KMAX>(tm.wave, incl, part, v, K, target, a0, a1, ai, c) || !c.hit) c.q = -1;
+    if (tm.lane == 0) tm.S->cand[tm.phase][0] = c;
+  }
+  block_lds_sync();
+  if (ow >= 0) {
+    c = tm.S->cand[tm.phase][0];
+    if (c.q >= 0) return c;
+  }
+  return pick_all_waves<KMAX>(tm, incl, part, v, K, target, a0, a1, ai);
+}
+
+// Outcome of an event for i (mass mi, swarm mass Mi) hitting j's swarm (mass
+// mj) at relative velocity dvj: new mass, outcome code and i's new record.
+// The writer also applies the side effects: the anomaly flag and the
+// mass-weighted composition of i on sticking or fragmentation (lanes below
+// n_comp, one component each).
+template <typename RT>
+__device__ inline int event_outcome(const CollideArgs &A, const TeamScratch *S, double mi,
+                                    double mj, double Mi, RT dvj, double u4, int gi, int gj,
+                                    int lane, bool writer, double &mnew, Rec<RT> &rin) {
+  const bool fast = !(dvj < (RT)A.P.v_frag);
+  const int oc = outcome(A.P, fast, mi, mj, u4, mnew);
+  if (writer) {
+    if ((!(mnew > 0.0) || !isfinite(mnew)) && lane == 0) atomicOr(&A.state->flags, FLAG_BAD_MASS);
+    if (A.comp != nullptr && A.P.n_comp > 0 && (oc == OUT_STICK || oc == OUT_FRAG) &&
+        lane < A.P.n_comp) {
+      const double wi = mi, wj = group_factor(A.P.dm_max, mi, mj) * mj;
+      float *cs = A.comp + (size_t)lane * A.N;
+      const double cI = (double)cs[gi], cJ = (double)cs[gj];
+      cs[gi] = (float)((wi * cI + wj * cJ) / (wi + wj));
+    }
+  }
+  rin = RecAfter<RT>::get(A.P, S, mnew, Mi);
+  return oc;
+}
+
+__device__ inline void log_event(const CollideArgs &A, int cell, int64_t e, int i_local,
+                                 int j_local, int oc) {
+  if (A.evlog != nullptr && e < A.log_per_cell) {
+    int32_t *L = A.evlog + ((size_t)cell * A.log_per_cell + e) * 4;
+    L[0] = i_local;
+    L[1] = j_local;
+    L[2] = oc;
+    L[3] = 0;
+  }
 }
 
 template <typename RT, int KMAX, bool FAST>
@@ -357,9 +446,13 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
   for (int q = 0; q < KMAX; ++q)
     if (q < K) part += r[q];
   double incl = tm.scan(part, Rtot);
-  // random words of 64 consecutive events: lane l holds Philox(e0 + l, cell,
-  // step, 0) and Philox(e0 + l, cell, step, 1); an event reads its lane
-  U4 rw0{0u, 0u, 0u, 0u}, rw1{0u, 0u, 0u, 0u};
+  // lanes from team lane 64 fix_wave on carry delta on top of the latest
+  // scanned prefix (the new row sum of the previous event's i)
+  int fix_wave = nw;
+  double delta = 0.0;
+  // uniforms of 64 consecutive events: lane l holds -ln u1, u2, u3, u4 of
+  // event e0 + l from Philox(e0 + l, cell, step, 0) and (.., 1)
+  double nlu1 = 0.0, uu2 = 0.0, uu3 = 0.0, uu4 = 0.0;
   int64_t e0 = -64;
   for (;;) {
     if (!(Rtot > 0.0) || !isfinite(Rtot)) {
@@ -370,23 +463,23 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     if (e - e0 >= 64) {
       e0 = e;
       const uint32_t ec = (uint32_t)(e + lane);
-      rw0 = philox4x32_10(U4{ec, c32, step, 0u}, A.P.key0, A.P.key1);
-      rw1 = philox4x32_10(U4{ec, c32, step, 1u}, A.P.key0, A.P.key1);
+      const U4 w0 = philox4x32_10(U4{ec, c32, step, 0u}, A.P.key0, A.P.key1);
+      const U4 w1 = philox4x32_10(U4{ec, c32, step, 1u}, A.P.key0, A.P.key1);
+      if (timed) nlu1 = -log(u01(w0.x, w0.y));
+      uu2 = u01(w0.z, w0.w);
+      uu3 = u01(w1.x, w1.y);
+      uu4 = u01(w1.z, w1.w);
     }
     const int rl = (int)(e - e0);
     if (timed) {
-      const double u1 = u01((uint32_t)readlane_i((int)rw0.x, rl), (uint32_t)readlane_i((int)rw0.y, rl));
-      const double tau = -log(u1) / Rtot * scale;  // exponential waiting time
+      const double tau = readlane_d(nlu1, rl) / Rtot * scale;  // exponential waiting time
       if (t + tau > A.dt) break;  // the next event falls outside the step
       t += tau;
     }
-    const double u2 = u01((uint32_t)readlane_i((int)rw0.z, rl), (uint32_t)readlane_i((int)rw0.w, rl));
-    const double u3 = u01((uint32_t)readlane_i((int)rw1.x, rl), (uint32_t)readlane_i((int)rw1.y, rl));
-    const double u4 = u01((uint32_t)readlane_i((int)rw1.z, rl), (uint32_t)readlane_i((int)rw1.w, rl));
 
-    // -- choose i by cumulative row sums (payloads: m_i, index)
-    const Cand ci = team_pick<KMAX, double, double>(tm, incl, part, r, K, u2 * Rtot, m64, r, m64,
-                                                    gix);
+    // -- choose i by cumulative row sums (payloads: m_i, old r_i, index)
+    const Cand ci = team_pick<KMAX>(tm, incl, part, r, K, readlane_d(uu2, rl) * Rtot, fix_wave,
+                                    delta, m64, r, gix);
     if (ci.q < 0) {
       if (tl == 0) atomicOr(&A.state->flags, FLAG_BAD_RATE);
       break;
@@ -422,57 +515,34 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
         for (int q = 0; q < KMAX; ++q)
           if (q == ci.q) r[q] = 0.0;
       }
-      if (tl == 0 && A.evlog != nullptr && e < A.log_per_cell) {
-        int32_t *L = A.evlog + ((size_t)cell * A.log_per_cell + e) * 4;
-        L[0] = i_local;
-        L[1] = -1;
-        L[2] = -1;
-        L[3] = 0;
-      }
+      if (tl == 0) log_event(A, cell, e, i_local, -1, -1);
       ++e;
       part = 0.0;
 #pragma unroll
       for (int q = 0; q < KMAX; ++q)
         if (q < K) part += r[q];
       incl = tm.scan(part, Rtot);
+      fix_wave = nw;
+      delta = 0.0;
       continue;
     }
-    // -- choose j (payloads: m_j, relative velocity, index)
-    const Cand cj = team_pick<KMAX, RT, RT>(tm, incl1, part1, rij, K, u3 * Ri, m64, m64, dvv, gix);
-    const int j_local = cj.lane * K + cj.q;
-    const double mj = cj.p0;
-    const RT dvj = (RT)cj.p2;
-    const int gj = cj.gi;
 
-    // -- outcome (only i changes)
-    double mnew;
-    const bool fast = !(dvj < (RT)A.P.v_frag);
-    const int oc = outcome(A.P, fast, mi, mj, u4, mnew);
-    if (!(mnew > 0.0) || !isfinite(mnew)) {
-      if (tl == 0) atomicOr(&A.state->flags, FLAG_BAD_MASS);
-    }
-    if (A.comp != nullptr && A.P.n_comp > 0 && (oc == OUT_STICK || oc == OUT_FRAG) &&
-        tl < A.P.n_comp) {
-      const double wi = mi, wj = group_factor(A.P.dm_max, mi, mj) * mj;
-      float *cs = A.comp + (size_t)tl * A.N;
-      const double cI = (double)cs[gi], cJ = (double)cs[gj];
-      cs[gi] = (float)((wi * cI + wj * cJ) / (wi + wj));
-    }
-    const Rec<RT> rin = RecAfter<RT>::get(A.P, tm.S, mnew, Mi);
+    // -- choose j (payloads: m_j, relative velocity, index), then the outcome
+    // (only i changes), computed alike by every wave; wave 0 writes
+    const Cand cj = team_pick<KMAX>(tm, incl1, part1, rij, K, readlane_d(uu3, rl) * Ri, nw, 0.0,
+                                    m64, dvv, gix);
+    double mnew = 0.0;
+    Rec<RT> rin;
+    const int oc = event_outcome<RT>(A, tm.S, mi, cj.p0, Mi, (RT)cj.p1, readlane_d(uu4, rl), gi,
+                                     cj.gi, lane, wave == 0, mnew, rin);
+    if (tl == 0) log_event(A, cell, e, i_local, cj.lane * K + cj.q, oc);
+    // the owner of i keeps the new mass and record; it alone reads the slot
+    // until the next exchange
     if (tl == ci.lane) {
 #pragma unroll
       for (int q = 0; q < KMAX; ++q)
         if (q == ci.q) m64[q] = mnew;
-    }
-    if (tl == 0) {
       R.store(si, rin);
-      if (A.evlog != nullptr && e < A.log_per_cell) {
-        int32_t *L = A.evlog + ((size_t)cell * A.log_per_cell + e) * 4;
-        L[0] = i_local;
-        L[1] = j_local;
-        L[2] = oc;
-        L[3] = 0;
-      }
     }
 
     // -- new row i: incremental update of the other rows, fresh row sum of i
@@ -481,7 +551,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     for (int q = 0; q < KMAX; ++q) {
       if (q < K) {
         const int s = q * TL + tl;
-        const Rec<RT> rq = s == si ? rin : R.load(s);
+        const Rec<RT> rq = R.load(s);
         RT dv, a_iq, a_qi;
         PairEval<RT, FAST>::run(pc, rin, rq, dv, a_iq, a_qi);
         part2 += (double)a_iq;
@@ -498,7 +568,8 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
       if (q < K) part += r[q];
     double ri_new;
     incl = tm.scan2(part, part2, Rtot, ri_new);
-    const double delta = ri_new - ri_old;
+    delta = ri_new - ri_old;
+    fix_wave = ci.lane >> 6;
     if (tl >= ci.lane) incl += delta;
     Rtot += delta;
     if (tl == ci.lane) {

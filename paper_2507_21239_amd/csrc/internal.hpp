@@ -55,7 +55,7 @@ struct Cand {
 };
 
 // team scratch after a region's particle records: wave totals, selection
-// candidates of each wave (double-buffered) and the cell's gas state
+// candidates (double-buffered) and the cell's gas state
 struct TeamScratch {
   double tot[2][8];
   Cand cand[2][4];
