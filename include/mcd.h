@@ -173,9 +173,42 @@ mcd_status mcd_rates(mcd_ctx *ctx, int32_t cell, double *r_out, int64_t ld, doub
 /* Advance n_steps global steps of length dt [s]: (re)bin when the grid is
  * adaptive, collide every cell, transport.  Inside a cell, events run until
  * the next waiting time would pass dt (dt > 0) and/or max_events_per_cell
- * events are done (> 0); at least one limit must be set.  Async; the
- * batched schedule replays a captured HIP graph when n_steps > 1. */
+ * events are done (> 0); at least one limit must be set.  Async.  With the
+ * batched schedule and n_steps > 1 one step is captured as a HIP graph
+ * (again after mcd_bin with explicit cells, mcd_tune, mcd_set_schedule or a
+ * change of dt or max_events) and replayed n_steps times; otherwise each
+ * step's kernels are launched directly. */
 mcd_status mcd_step(mcd_ctx *ctx, double dt, int64_t max_events_per_cell, int32_t n_steps);
+
+/* Schedule of the batched collision launch (one persistent launch over all
+ * cells, largest cells first): which team shape processes a cell and how
+ * many workgroups run at once.  Results depend on it only through the
+ * rounding order of the FP64 prefix scans, which follows the team layout. */
+typedef struct {
+  int32_t small_max;   /* cells of up to small_max particles run on one
+                          wavefront, larger ones on teams of four (0..512) */
+  int32_t grid_per_cu; /* persistent workgroups per compute unit; 0 = as many
+                          as the kernel's registers and LDS allow */
+  int32_t trials;      /* configurations timed by mcd_tune */
+  int32_t pad;
+  double ms_best;      /* collision-launch time of the chosen schedule [ms] */
+  double ms_default;   /* ... of the schedule in force before tuning [ms] */
+} mcd_tune_result;
+
+/* Autotuner of the batched schedule on the current cells: times one
+ * collision launch (dt, max_events_per_cell as in mcd_step) for each
+ * single-wave threshold in {0, 64, 128, 192, 256, 384, 512} that gives a
+ * distinct, fitting plan, then 1 and 2 workgroups per compute unit at the
+ * best threshold, and keeps the fastest.  Masses, compositions and counters
+ * are restored after every trial (the step counter does not advance; no
+ * event log is written).  Synchronises; MCD_EINVAL for the plain schedule,
+ * MCD_ESTATE before mcd_bin. */
+mcd_status mcd_tune(mcd_ctx *ctx, double dt, int64_t max_events_per_cell, mcd_tune_result *out);
+
+/* Set the batched schedule directly (e.g. a stored tuning result).
+ * MCD_EINVAL if out of range or if the plan does not fit the GPU's LDS (the
+ * previous schedule is kept). */
+mcd_status mcd_set_schedule(mcd_ctx *ctx, int32_t small_max, int32_t grid_per_cu);
 
 /* Copy the counters to the host (synchronises) and report the sticky
  * device flag as MCD_EDEVICE. */

@@ -26,8 +26,9 @@ GAS_FIELDS = 6
 GEOM_FIELDS = 5
 
 # every function declared in include/mcd.h
-EXPORTS = ("mcd_init", "mcd_bin", "mcd_rates", "mcd_step", "mcd_get_stats", "mcd_get_cells",
-           "mcd_set_event_log", "mcd_philox", "mcd_last_error", "mcd_free")
+EXPORTS = ("mcd_init", "mcd_bin", "mcd_rates", "mcd_step", "mcd_tune", "mcd_set_schedule",
+           "mcd_get_stats", "mcd_get_cells", "mcd_set_event_log", "mcd_philox", "mcd_last_error",
+           "mcd_free")
 
 
 class Params(C.Structure):
@@ -47,6 +48,11 @@ class Particles(C.Structure):
 class Cells(C.Structure):
     _fields_ = [("n_cells", C.c_int32), ("cell_start", C.c_void_p), ("order", C.c_void_p),
                 ("gas", C.c_void_p)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("small_max", C.c_int32), ("grid_per_cu", C.c_int32), ("trials", C.c_int32),
+                ("pad", C.c_int32), ("ms_best", C.c_double), ("ms_default", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -73,6 +79,8 @@ def load() -> C.CDLL:
         "mcd_bin": (i32, [vp, C.POINTER(Cells)]),
         "mcd_rates": (i32, [vp, i32, vp, i64, vp]),
         "mcd_step": (i32, [vp, C.c_double, i64, i32]),
+        "mcd_tune": (i32, [vp, C.c_double, i64, C.POINTER(TuneResult)]),
+        "mcd_set_schedule": (i32, [vp, i32, i32]),
         "mcd_get_stats": (i32, [vp, C.POINTER(Stats)]),
         "mcd_get_cells": (i32, [vp, vp, vp, vp, vp]),
         "mcd_set_event_log": (i32, [vp, vp, i64]),

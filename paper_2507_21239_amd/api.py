@@ -79,6 +79,17 @@ class Simulation:
     def step(self, dt: float, max_events: int = 0, n_steps: int = 1) -> None:
         self._check(self.lib.mcd_step(self.ctx, float(dt), int(max_events), int(n_steps)), "mcd_step")
 
+    def tune(self, dt: float, max_events: int = 0) -> dict:
+        """Autotune the batched schedule on the current cells (state kept)."""
+        r = _lib.TuneResult()
+        self._check(self.lib.mcd_tune(self.ctx, float(dt), int(max_events), C.byref(r)), "mcd_tune")
+        return dict(small_max=r.small_max, grid_per_cu=r.grid_per_cu, trials=r.trials,
+                    ms_best=r.ms_best, ms_default=r.ms_default)
+
+    def set_schedule(self, small_max: int, grid_per_cu: int = 0) -> None:
+        self._check(self.lib.mcd_set_schedule(self.ctx, int(small_max), int(grid_per_cu)),
+                    "mcd_set_schedule")
+
     def rates(self, cell: int, n: int) -> tuple[torch.Tensor, torch.Tensor]:
         out = torch.empty((max(n, 1), max(n, 1)), dtype=torch.float64, device=self.t["m"].device)
         rs = torch.empty(max(n, 1), dtype=torch.float64, device=self.t["m"].device)

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -36,12 +37,22 @@ struct mcd_ctx {
   bool g_valid = false;
   double g_dt = 0.0;
   int64_t g_max = 0;
+  // schedule of the batched launch (set by mcd_tune): cells up to small_max
+  // particles run on one wave, larger ones on four-wave teams; grid_per_cu
+  // persistent workgroups per compute unit (0: as many as fit)
+  int small_max = 256;
+  int grid_per_cu = 0;
+  int cus = 0;
+  std::vector<int32_t> sizes;  // particle count of every cell of the grid
+  double *d_mbak = nullptr;    // tuning backups of m, comp and the device state
+  float *d_cbak = nullptr;
+  DevState *d_sbak = nullptr;
   std::string err;
 };
 
 namespace {
 
-constexpr int kSmallMax = 256;        // cells up to this size run on one wave
+constexpr int kSmallLimit = 512;      // largest single-wave cell a schedule may choose
 constexpr int kBigMax = 2048;         // largest cell of the batched schedule
 constexpr int kPlainMax = 2048;       // largest cell of the plain schedule
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
@@ -200,8 +211,9 @@ mcd_status alloc_binning(mcd_ctx *c, int64_t N) {
 mcd_status plan_lists(mcd_ctx *c, const std::vector<int32_t> &sizes) {
   std::vector<int32_t> big, small;
   int32_t mb = 0, ms = 0;
+  c->sizes = sizes;
   for (int32_t k = 0; k < (int32_t)sizes.size(); ++k) {
-    if (sizes[k] > kSmallMax) {
+    if (sizes[k] > c->small_max) {
       big.push_back(k);
       mb = std::max(mb, sizes[k]);
     } else if (sizes[k] > 0) {
@@ -226,11 +238,14 @@ mcd_status plan_lists(mcd_ctx *c, const std::vector<int32_t> &sizes) {
   const size_t lds = c->prm.schedule == MCD_SCHED_PLAIN ? lds_big : std::max(lds_big, lds_small);
   if (lds > kLdsBytes)
     return fail(c, MCD_EINVAL, "largest cell does not fit the 160 KB LDS in this precision");
+  // in stream order, so that work already queued still sees the old lists
   if (!big.empty())
-    MCD_HIP(c, hipMemcpy(c->d_big, big.data(), big.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    MCD_HIP(c, hipMemcpyAsync(c->d_big, big.data(), big.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, c->stream));
   if (!small.empty())
-    MCD_HIP(c, hipMemcpy(c->d_small, small.data(), small.size() * sizeof(int32_t),
-                         hipMemcpyHostToDevice));
+    MCD_HIP(c, hipMemcpyAsync(c->d_small, small.data(), small.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, c->stream));
+  MCD_HIP(c, hipStreamSynchronize(c->stream));
   return MCD_OK;
 }
 
@@ -275,7 +290,8 @@ mcd_status enqueue_step(mcd_ctx *c, double dt, int64_t max_events, hipStream_t s
   if (c->adaptive && (st = enqueue_bin(c, s)) != MCD_OK) return st;
   if (c->prm.flags & COAG) {
     hipError_t e = launch_collide(collide_args(c, dt, max_events), c->prm.precision,
-                                  c->prm.schedule, c->n_cells, c->max_cell, 0, s);
+                                  c->prm.schedule, c->n_cells, c->max_cell,
+                                  c->grid_per_cu * c->cus, s);
     if (e != hipSuccess) return hip_fail(c, e, "collide");
   }
   if (c->adaptive && transport_on(c)) {
@@ -313,6 +329,9 @@ mcd_status mcd_init(const mcd_params *params, const mcd_particles *particles, vo
   hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipMalloc((void **)&c->d_state, sizeof(DevState));
   if (e == hipSuccess) e = hipMemset(c->d_state, 0, sizeof(DevState));
+  int dev = 0;
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) {
     mcd_free(c);
     return e == hipErrorOutOfMemory ? MCD_ENOMEM : MCD_EHIP;
@@ -451,6 +470,136 @@ mcd_status mcd_step(mcd_ctx *c, double dt, int64_t max_events, int32_t n_steps) 
   return MCD_OK;
 }
 
+mcd_status mcd_set_schedule(mcd_ctx *c, int32_t small_max, int32_t grid_per_cu) {
+  if (!c) return MCD_EINVAL;
+  if (small_max < 0 || small_max > kSmallLimit || grid_per_cu < 0 || grid_per_cu > 64)
+    return fail(c, MCD_EINVAL, "small_max must be in [0, 512], grid_per_cu in [0, 64]");
+  const int sm0 = c->small_max, g0 = c->grid_per_cu;
+  c->small_max = small_max;
+  c->grid_per_cu = grid_per_cu;
+  if (c->have_cells) {
+    mcd_status st = plan_lists(c, c->sizes);
+    if (st != MCD_OK) {
+      c->small_max = sm0;
+      c->grid_per_cu = g0;
+      (void)plan_lists(c, c->sizes);
+      return st;
+    }
+  }
+  drop_graph(c);
+  return MCD_OK;
+}
+
+mcd_status mcd_tune(mcd_ctx *c, double dt, int64_t max_events, mcd_tune_result *out) {
+  if (!c || !out) return MCD_EINVAL;
+  if (!c->have_cells) return fail(c, MCD_ESTATE, "mcd_tune before mcd_bin");
+  if (c->prm.schedule != MCD_SCHED_BATCHED)
+    return fail(c, MCD_EINVAL, "mcd_tune applies to the batched schedule");
+  if (!(std::isfinite(dt) && dt >= 0.0) || max_events < 0 || max_events >= ((int64_t)1 << 32))
+    return fail(c, MCD_EINVAL, "dt and max_events must be >= 0, max_events < 2^32");
+  if (!(dt > 0.0) && max_events == 0)
+    return fail(c, MCD_EINVAL, "set a time limit dt > 0 or max_events > 0");
+  std::memset(out, 0, sizeof(*out));
+  out->small_max = c->small_max;
+  out->grid_per_cu = c->grid_per_cu;
+  if (!(c->prm.flags & COAG)) return MCD_OK;
+  const int64_t N = c->part.n;
+  const size_t ncomp = c->part.comp ? (size_t)c->prm.n_comp * (size_t)N : 0;
+  if (!c->d_mbak) {
+    if (dalloc(&c->d_mbak, (size_t)N) != hipSuccess || dalloc(&c->d_sbak, 1) != hipSuccess ||
+        (ncomp && dalloc(&c->d_cbak, ncomp) != hipSuccess))
+      return fail(c, MCD_ENOMEM, "device allocation of the tuning backups failed");
+  }
+  hipStream_t s = c->stream;
+  MCD_HIP(c, hipMemcpyAsync(c->d_mbak, c->part.m, (size_t)N * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+  if (ncomp)
+    MCD_HIP(c, hipMemcpyAsync(c->d_cbak, c->part.comp, ncomp * sizeof(float),
+                              hipMemcpyDeviceToDevice, s));
+  MCD_HIP(c, hipMemcpyAsync(c->d_sbak, c->d_state, sizeof(DevState), hipMemcpyDeviceToDevice, s));
+  auto restore = [&]() -> hipError_t {
+    hipError_t e = hipMemcpyAsync(c->part.m, c->d_mbak, (size_t)N * sizeof(double),
+                                  hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && ncomp)
+      e = hipMemcpyAsync(c->part.comp, c->d_cbak, ncomp * sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->d_state, c->d_sbak, sizeof(DevState), hipMemcpyDeviceToDevice, s);
+    return e;
+  };
+  int32_t *const evlog = c->evlog;
+  c->evlog = nullptr;  // trial runs leave no event log
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  hipError_t herr = hipEventCreate(&ev_a);
+  if (herr == hipSuccess) herr = hipEventCreate(&ev_b);
+  // time one collision launch per configuration, state restored before each
+  auto trial = [&](int sm, int gpc, double &ms) -> bool {
+    c->small_max = sm;
+    c->grid_per_cu = gpc;
+    if (plan_lists(c, c->sizes) != MCD_OK) return false;  // does not fit this GPU
+    for (int rep = 0; rep < 2 && herr == hipSuccess; ++rep) {
+      herr = restore();
+      if (herr == hipSuccess && rep == 1) herr = hipEventRecord(ev_a, s);
+      if (herr == hipSuccess)
+        herr = launch_collide(collide_args(c, dt, max_events), c->prm.precision, c->prm.schedule,
+                              c->n_cells, c->max_cell, gpc * c->cus, s);
+      if (herr == hipSuccess && rep == 1) herr = hipEventRecord(ev_b, s);
+    }
+    float f = 0.0f;
+    if (herr == hipSuccess) herr = hipEventSynchronize(ev_b);
+    if (herr == hipSuccess) herr = hipEventElapsedTime(&f, ev_a, ev_b);
+    ms = f;
+    ++out->trials;
+    return herr == hipSuccess;
+  };
+  const int sm0 = c->small_max, g0 = c->grid_per_cu;
+  double best = 0.0, t = 0.0;
+  int best_sm = sm0, best_g = g0;
+  // single-wave threshold at the full grid, then the grid at that threshold;
+  // thresholds giving the same lists as one already timed are skipped
+  std::vector<std::array<int, 4>> seen;
+  if (trial(sm0, g0, t)) {
+    best = t;
+    out->ms_default = t;
+    if (g0 == 0) seen.push_back({c->n_big, c->n_small, c->big_cap, c->small_cap});
+  }
+  const int sms[] = {0, 64, 128, 192, 256, 384, 512};
+  for (int sm : sms) {
+    if (herr != hipSuccess) break;
+    c->small_max = sm;
+    if (plan_lists(c, c->sizes) != MCD_OK) continue;
+    const std::array<int, 4> key{c->n_big, c->n_small, c->big_cap, c->small_cap};
+    if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
+    seen.push_back(key);
+    if (trial(sm, 0, t) && (best == 0.0 || t < best)) {
+      best = t;
+      best_sm = sm;
+      best_g = 0;
+    }
+  }
+  for (int gpc : {1, 2}) {
+    if (herr != hipSuccess) break;
+    if (trial(best_sm, gpc, t) && (best == 0.0 || t < best)) {
+      best = t;
+      best_g = gpc;
+    }
+  }
+  if (ev_a) (void)hipEventDestroy(ev_a);
+  if (ev_b) (void)hipEventDestroy(ev_b);
+  c->evlog = evlog;
+  c->small_max = best_sm;
+  c->grid_per_cu = best_g;
+  mcd_status st = plan_lists(c, c->sizes);
+  if (herr == hipSuccess) herr = restore();
+  if (herr == hipSuccess) herr = hipStreamSynchronize(s);
+  drop_graph(c);
+  if (herr != hipSuccess) return hip_fail(c, herr, "mcd_tune");
+  if (st != MCD_OK) return st;
+  out->small_max = best_sm;
+  out->grid_per_cu = best_g;
+  out->ms_best = best;
+  return MCD_OK;
+}
+
 mcd_status mcd_get_stats(mcd_ctx *c, mcd_stats *o) {
   if (!c || !o) return MCD_EINVAL;
   DevState s{};
@@ -525,6 +674,9 @@ void mcd_free(mcd_ctx *c) {
   free_grid(c);
   BinBuffers &b = c->bb;
   free_binning(b);
+  dfree(c->d_mbak);
+  dfree(c->d_cbak);
+  dfree(c->d_sbak);
   dfree(c->d_state);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;

@@ -20,6 +20,8 @@
 // 16-byte words.  Row sums (FP64), the per-event row values, masses and
 // particle indices stay in registers of the owning lane; masses go back to
 // HBM once, when the cell is done.
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "internal.hpp"
 
@@ -733,7 +735,12 @@ static bool fast_path(const CollideArgs &a, int precision) {
 
 hipError_t launch_collide(const CollideArgs &a, int precision, int schedule, int n_cells,
                           int max_cell, int grid_override, hipStream_t s) {
-  const bool wide = max_cell > 1024;
+  // slots per lane: four-wave teams hold big_cap particles, single waves
+  // small_cap; kernels exist for up to 4 and up to 8
+  const int k_big = (a.big_cap + 255) / 256, k_small = (a.small_cap + 63) / 64;
+  const int kneed = schedule == 0 ? std::max(k_big, (max_cell + 255) / 256) : std::max(k_big, k_small);
+  if (kneed > 8) return hipErrorInvalidValue;
+  const bool wide = kneed > 4;
   const bool fast = fast_path(a, precision);
   if (schedule == 0) {
     if (precision == 0)

@@ -28,7 +28,7 @@ def run_oracle_explicit(work: dict, log_per_cell: int = 0, step: int = 0, thread
 
 
 def run_gpu_explicit(work: dict, precision: str, schedule: str, log_per_cell: int = 0,
-                     n_steps: int = 1):
+                     n_steps: int = 1, batched_schedule=None):
     import torch
     from paper_2507_21239_amd import api
     say(work["name"], precision, schedule, "cells", len(work["cells"]["cell_start"]) - 1,
@@ -36,6 +36,8 @@ def run_gpu_explicit(work: dict, precision: str, schedule: str, log_per_cell: in
     dev = api.to_device(work["particles"])
     sim = api.Simulation(work["params"], dev, precision=precision, schedule=schedule)
     sim.bin(api.cells_to_device(work["cells"]))
+    if batched_schedule is not None:
+        sim.set_schedule(*batched_schedule)
     nc = len(work["cells"]["cell_start"]) - 1
     log = None
     if log_per_cell:

@@ -36,7 +36,8 @@ def test_library_exports_every_declared_function():
 def test_struct_layouts_match_header(tmp_path):
     src = tmp_path / "layout.c"
     structs = {"mcd_params": _lib.Params, "mcd_particles": _lib.Particles,
-               "mcd_cells": _lib.Cells, "mcd_stats": _lib.Stats}
+               "mcd_cells": _lib.Cells, "mcd_stats": _lib.Stats,
+               "mcd_tune_result": _lib.TuneResult}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mcd.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -98,4 +99,6 @@ def test_null_context_calls_are_rejected():
     assert lib.mcd_get_stats(None, None) == _lib.MCD_EINVAL
     assert lib.mcd_last_error(None) == b"null context"
     assert lib.mcd_philox(None, 0, 0, None, -1, None) == _lib.MCD_EINVAL
+    assert lib.mcd_tune(None, 1.0, 0, None) == _lib.MCD_EINVAL
+    assert lib.mcd_set_schedule(None, 256, 0) == _lib.MCD_EINVAL
     lib.mcd_free(None)
