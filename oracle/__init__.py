@@ -88,6 +88,8 @@ def lib():
             "orc_transport": (None, [P, C.c_int64, dp, dp, dp, u8p, C.c_uint32, C.c_double]),
             "orc_collide_all": (None, [P, C.c_int32, ip, ip, dp, C.c_uint32, dp, dp, fp, C.c_int64,
                                        C.c_double, C.c_int64, vp, C.c_int64, vp, C.c_int32]),
+            "orc_sigma_hist": (C.c_int64, [C.c_int64, dp, dp, dp, u8p, dp, C.c_int32, dp, C.c_int32,
+                                           C.c_int32, dp, C.POINTER(C.c_uint32)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -239,6 +241,24 @@ def transport(params: dict, part: dict, step: int, dt: float) -> None:
     assert act.dtype == np.uint8
     lib().orc_transport(C.byref(make_params(params)), len(r), _ptr(r, C.c_double), _ptr(z, C.c_double),
                         _ptr(m, C.c_double), _ptr(act, C.c_uint8), step, dt)
+
+
+def sigma_hist(part: dict, r_edges, m_edges, column: bool = False) -> tuple:
+    """sigma_d(m, r) of the active particles: (sigma [n_rb, n_mb] in g/cm^2 per
+    mass bin, count [n_rb, n_mb], particles counted)."""
+    r = np.ascontiguousarray(part["r"], dtype=np.float64)
+    m = np.ascontiguousarray(part["m"], dtype=np.float64)
+    M = np.ascontiguousarray(part["M"], dtype=np.float64)
+    act = np.ascontiguousarray(part["active"], dtype=np.uint8)
+    re = np.ascontiguousarray(r_edges, dtype=np.float64)
+    me = np.ascontiguousarray(m_edges, dtype=np.float64)
+    nr, nm = len(re) - 1, len(me) - 1
+    sigma = np.zeros((nr, nm))
+    count = np.zeros((nr, nm), dtype=np.uint32)
+    n = lib().orc_sigma_hist(len(r), _ptr(r, C.c_double), _ptr(m, C.c_double), _ptr(M, C.c_double),
+                             _ptr(act, C.c_uint8), _ptr(re, C.c_double), nr, _ptr(me, C.c_double), nm,
+                             1 if column else 0, _ptr(sigma, C.c_double), _ptr(count, C.c_uint32))
+    return sigma, count, int(n)
 
 
 def transport_on(params: dict) -> bool:

@@ -550,3 +550,45 @@ void orc_transport(const orc_params *P, int64_t N, double *r, double *z, const d
     }
   }
 }
+
+/* ------------------------------------------------------------------------
+ * sigma_d(m, r) (paper, Benchmark: surface density by particle mass and
+ * distance from the star)
+ * ------------------------------------------------------------------------ */
+/* index k with e[k] <= x < e[k+1], or -1 outside [e[0], e[n]) */
+static int32_t orc_find_bin(const double *e, int32_t n, double x) {
+  if (!(x >= e[0]) || !(x < e[n])) return -1;
+  int32_t lo = 0, hi = n; /* e[lo] <= x < e[hi] */
+  while (hi - lo > 1) {
+    const int32_t mid = lo + (hi - lo) / 2;
+    if (x < e[mid]) hi = mid; else lo = mid;
+  }
+  return lo;
+}
+
+int64_t orc_sigma_hist(int64_t N, const double *r, const double *m, const double *M,
+                       const uint8_t *active, const double *r_edges, int32_t n_rb,
+                       const double *m_edges, int32_t n_mb, int32_t column, double *sigma,
+                       uint32_t *count) {
+  const int64_t nb = (int64_t)n_rb * n_mb;
+  for (int64_t b = 0; b < nb; ++b) {
+    sigma[b] = 0.0;
+    if (count) count[b] = 0u;
+  }
+  int64_t counted = 0;
+  for (int64_t i = 0; i < N; ++i) {
+    if (!active[i]) continue;
+    const int32_t k = orc_find_bin(r_edges, n_rb, r[i]);
+    const int32_t l = orc_find_bin(m_edges, n_mb, m[i]);
+    if (k < 0 || l < 0) continue;
+    sigma[(int64_t)k * n_mb + l] += M[i];
+    if (count) count[(int64_t)k * n_mb + l] += 1u;
+    ++counted;
+  }
+  for (int32_t k = 0; k < n_rb; ++k) {
+    const double area = column ? 1.0
+                               : PI * (r_edges[k + 1] * r_edges[k + 1] - r_edges[k] * r_edges[k]);
+    for (int32_t l = 0; l < n_mb; ++l) sigma[(int64_t)k * n_mb + l] /= area;
+  }
+  return counted;
+}

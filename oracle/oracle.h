@@ -143,6 +143,21 @@ int64_t orc_collide_cell(const orc_params *P, const double prim[ORC_GAS_FIELDS],
 void orc_transport(const orc_params *P, int64_t N, double *r, double *z, const double *m,
                    uint8_t *active, uint32_t step, double dt);
 
+/* sigma_d(m, r), the dust surface density per mass bin (paper, Benchmark:
+ * the run's output is the dust surface density as a function of particle mass
+ * and distance from the star).  Bins are half-open, r_edges[k] <= r <
+ * r_edges[k+1] and m_edges[l] <= m < m_edges[l+1], edges strictly
+ * increasing.  For every active particle in range, its swarm mass M is added
+ * to bin (k, l) in particle order; then each bin is divided by its annulus
+ * area pi (r_edges[k+1]^2 - r_edges[k]^2) (area 1 in column mode, where M is
+ * already per unit area).  sigma[k*n_mb + l] in g/cm^2 per mass bin, count[]
+ * the number of representative particles (count may be NULL).  Returns the
+ * number of particles counted. */
+int64_t orc_sigma_hist(int64_t N, const double *r, const double *m, const double *M,
+                       const uint8_t *active, const double *r_edges, int32_t n_rb,
+                       const double *m_edges, int32_t n_mb, int32_t column, double *sigma,
+                       uint32_t *count);
+
 /* all cells of one step: collide every cell (threads over cells).
  * log may be NULL; otherwise cell c writes log[c*log_per_cell ...] */
 void orc_collide_all(const orc_params *P, int32_t n_cells, const int32_t *cell_start,
