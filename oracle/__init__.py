@@ -28,7 +28,11 @@ class Params(C.Structure):
         "sigma_g0", "T0", "p", "q", "alpha", "v_frag", "erosion_ratio", "a_mono", "rho_s",
         "mu", "m_star", "r_ref", "dm_max", "erosion_chi", "r_in", "r_col", "k0")] + [
         ("kernel", C.c_int32), ("n_r", C.c_int32), ("n_z", C.c_int32), ("column", C.c_int32),
-        ("flags", C.c_uint32), ("n_comp", C.c_int32), ("seed", C.c_uint64)]
+        ("flags", C.c_uint32), ("n_comp", C.c_int32), ("seed", C.c_uint64),
+        ("frag_mode", C.c_int32), ("pad_", C.c_int32), ("frag_width", C.c_double)]
+
+
+FRAG_MODES = {"sharp": 0, "ramp": 1, "maxwell": 2}
 
 
 class Gas(C.Structure):
@@ -80,7 +84,9 @@ def lib():
             "orc_rate": (C.c_double, [P, G, Q, Q]),
             "orc_frag_draw": (C.c_double, [C.c_double, C.c_double, C.c_double]),
             "orc_select": (C.c_int32, [dp, C.c_int32, C.c_double]),
-            "orc_outcome": (C.c_int32, [P, C.c_double, C.c_double, C.c_double, C.c_double, dp]),
+            "orc_outcome": (C.c_int32, [P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                                        dp]),
+            "orc_frag_probability": (C.c_double, [P, C.c_double]),
             "orc_cell_rates": (None, [P, dp, C.c_int32, ip, dp, dp, dp, dp]),
             "orc_bin": (C.c_int64, [P, C.c_int64, dp, dp, u8p, ip, ip, dp, dp]),
             "orc_collide_cell": (C.c_int64, [P, dp, C.c_int32, C.c_uint32, C.c_int32, ip, dp, dp, fp,
@@ -111,6 +117,13 @@ def make_params(d: dict) -> Params:
         elif name == "flags":
             fl = d["flags"]
             p.flags = sum(FLAG_BITS[f] for f in fl) if not isinstance(fl, int) else fl
+        elif name == "frag_mode":
+            fm = d.get("frag_mode", 0)
+            p.frag_mode = FRAG_MODES[fm] if isinstance(fm, str) else int(fm)
+        elif name == "frag_width":
+            p.frag_width = d.get("frag_width", 0.0)
+        elif name == "pad_":
+            pass
         else:
             setattr(p, name, d[name])
     return p
@@ -172,10 +185,16 @@ def select(v, target: float) -> int:
     return int(lib().orc_select(_ptr(a, C.c_double), len(a), target))
 
 
-def outcome(params: dict, dv: float, mi: float, mj: float, u: float) -> tuple[str, float]:
+def outcome(params: dict, dv: float, mi: float, mj: float, u: float,
+            uf: float = 0.5) -> tuple[str, float]:
+    """uf: the uniform of the fragmentation decision (unused when sharp)."""
     mn = C.c_double()
-    code = lib().orc_outcome(C.byref(make_params(params)), dv, mi, mj, u, C.byref(mn))
+    code = lib().orc_outcome(C.byref(make_params(params)), dv, mi, mj, u, uf, C.byref(mn))
     return OUTCOMES[code], mn.value
+
+
+def frag_probability(params: dict, dv: float) -> float:
+    return lib().orc_frag_probability(C.byref(make_params(params)), dv)
 
 
 def cell_rates(params: dict, prim, members, m, M) -> tuple[np.ndarray, np.ndarray]:

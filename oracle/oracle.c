@@ -238,14 +238,39 @@ static double orc_m0(const orc_params *P) {
 /* outcome of a collision of representative particle i (mass mi) with a
  * member of swarm j (mass mj): sticking below v_frag; otherwise erosion when
  * the mass ratio reaches erosion_ratio, else fragmentation.  Only i changes. */
-int32_t orc_outcome(const orc_params *P, double dv, double mi, double mj, double u,
+/* Fragmentation criterion.  Sharp: fragment iff dv >= v_frag (the paper's
+ * fragmentation velocity).  Ramp: the probability rises linearly from 0 at
+ * (1 - w) v_frag to 1 at v_frag.  Maxwell: the collision speed follows the
+ * Maxwell speed distribution whose mean is dv (scale a = dv sqrt(pi/8)), and
+ * the probability is the tail above v_frag,
+ * erfc(x) + 2/sqrt(pi) x exp(-x^2) with x = v_frag / (sqrt(2) a). */
+double orc_frag_probability(const orc_params *P, double dv) {
+  const double vf = P->v_frag;
+  if (P->frag_mode == ORC_FRAG_RAMP) {
+    const double lo = (1.0 - P->frag_width) * vf;
+    if (dv <= lo) return 0.0;
+    if (dv >= vf) return 1.0;
+    return (dv - lo) / (vf - lo);
+  }
+  if (P->frag_mode == ORC_FRAG_MAXWELL) {
+    if (!(dv > 0.0)) return 0.0;
+    const double x = 2.0 * vf / (sqrt(PI) * dv);
+    return erfc(x) + 2.0 / sqrt(PI) * x * exp(-x * x);
+  }
+  return dv < vf ? 0.0 : 1.0;
+}
+
+/* uf: the uniform of the fragmentation decision (used unless sharp) */
+int32_t orc_outcome(const orc_params *P, double dv, double mi, double mj, double u, double uf,
                     double *m_new) {
   double grp = 1.0;
   if (P->dm_max > 0.0) {
     grp = P->dm_max * mi / mj;
     if (grp < 1.0) grp = 1.0;
   }
-  if (P->kernel != ORC_K_PHYSICAL || dv < P->v_frag) {
+  const int fast = P->frag_mode == ORC_FRAG_SHARP ? !(dv < P->v_frag)
+                                                  : uf < orc_frag_probability(P, dv);
+  if (P->kernel != ORC_K_PHYSICAL || !fast) {
     *m_new = mi + grp * mj;
     return ORC_OUT_STICK;
   }
@@ -429,8 +454,10 @@ int64_t orc_collide_cell(const orc_params *P, const double prim[ORC_GAS_FIELDS],
     double dv = (P->kernel == ORC_K_PHYSICAL) ? orc_rel_velocity(P, &g, &pp[i], &pp[j]) : 0.0;
     for (int32_t k = 0; k < n; ++k) col[k] = orc_rate(P, &g, &pp[k], &pp[i]);
 
-    double mi = pp[i].m, mj = pp[j].m, mnew;
-    int32_t oc = orc_outcome(P, dv, mi, mj, u4, &mnew);
+    double mi = pp[i].m, mj = pp[j].m, mnew, u5 = 0.0, u6;
+    if (P->frag_mode != ORC_FRAG_SHARP)
+      orc_uniforms(P, (uint32_t)e, (uint32_t)cell_id, step, 3u, &u5, &u6);
+    int32_t oc = orc_outcome(P, dv, mi, mj, u4, u5, &mnew);
     if (comp && P->n_comp > 0 && (oc == ORC_OUT_STICK || oc == ORC_OUT_FRAG)) {
       double grp = 1.0;
       if (P->dm_max > 0.0) {

@@ -41,6 +41,11 @@ extern "C" {
 #define ORC_TR_MIX_Z (1u << 11)
 #define ORC_COAG (1u << 12)
 
+/* fragmentation criterion (outcome variants of the cited literature) */
+#define ORC_FRAG_SHARP 0     /* fragment iff dv >= v_frag */
+#define ORC_FRAG_RAMP 1      /* probability rising linearly over [(1 - w) v_frag, v_frag] */
+#define ORC_FRAG_MAXWELL 2   /* collision speeds Maxwellian with mean dv: P(speed >= v_frag) */
+
 /* outcome codes written to the event log */
 #define ORC_OUT_STICK 0
 #define ORC_OUT_ERODE 1      /* i is the larger body and loses mass */
@@ -70,6 +75,9 @@ typedef struct {
   uint32_t flags;       /* ORC_DV_* | ORC_TR_* | ORC_COAG */
   int32_t n_comp;       /* composition fractions per particle (0..8) */
   uint64_t seed;        /* Philox key */
+  int32_t frag_mode;    /* ORC_FRAG_*: how the relative velocity decides fragmentation */
+  int32_t pad_;
+  double frag_width;    /* ORC_FRAG_RAMP: relative width of the ramp below v_frag */
 } orc_params;
 
 /* per-cell gas record, six primaries: V, rho_g, T, alpha, r_c, zeta (= z_c/H) */
@@ -114,8 +122,11 @@ double orc_pair_kernel(const orc_params *P, const orc_gas *g, const orc_particle
 double orc_rate(const orc_params *P, const orc_gas *g, const orc_particle *pi,
                 const orc_particle *pj);
 double orc_frag_draw(double lo, double hi, double u);
+/* probability that a collision at mean relative velocity dv fragments
+ * (or erodes), by P->frag_mode */
+double orc_frag_probability(const orc_params *P, double dv);
 int32_t orc_select(const double *v, int32_t n, double target);
-int32_t orc_outcome(const orc_params *P, double dv, double mi, double mj, double u,
+int32_t orc_outcome(const orc_params *P, double dv, double mi, double mj, double u, double uf,
                     double *m_new);
 
 /* --- the method --- */

@@ -40,7 +40,7 @@ def benchmark_params(**over) -> dict:
         dm_max=1e-3, erosion_chi=1.0, r_in=AU, r_col=AU, k0=1.0,
         kernel="physical", n_r=1, n_z=1, column=0,
         flags=list(VELOCITY_SOURCES) + ["coag"],
-        n_comp=0, seed=0,
+        n_comp=0, seed=0, frag_mode="sharp", frag_width=0.2,
     )
     p.update(over)
     return p
