@@ -74,6 +74,17 @@ typedef enum {
                                four-wave teams, small cells on single waves;
                                multi-step loops replayed from a HIP graph */
 
+/* fragmentation criterion of a collision at relative velocity dv (outcome
+ * variants of the literature the paper cites for its collision physics):
+ * SHARP fragments iff dv >= v_frag; RAMP with probability rising linearly
+ * from 0 at (1 - w) v_frag to 1 at v_frag; MAXWELL with the probability that
+ * a Maxwellian collision speed of mean dv exceeds v_frag,
+ * erfc(x) + 2/sqrt(pi) x exp(-x^2), x = 2 v_frag / (sqrt(pi) dv).  RAMP and
+ * MAXWELL draw their uniform from Philox counter (event, cell, step, 3). */
+#define MCD_FRAG_SHARP 0
+#define MCD_FRAG_RAMP 1
+#define MCD_FRAG_MAXWELL 2
+
 /* outcome codes (event log and statistics) */
 #define MCD_OUT_STICK 0
 #define MCD_OUT_ERODE 1        /* i is the larger body and loses mass */
@@ -110,6 +121,9 @@ typedef struct {
   uint64_t seed;        /* Philox4x32-10 key (low word, high word) */
   int32_t precision;    /* MCD_FP64 | MCD_MIXED */
   int32_t schedule;     /* MCD_SCHED_PLAIN | MCD_SCHED_BATCHED */
+  int32_t frag_mode;    /* MCD_FRAG_*: how the relative velocity decides fragmentation */
+  int32_t pad;
+  double frag_width;    /* MCD_FRAG_RAMP: relative width w of the ramp, 0 < w <= 1 */
 } mcd_params;
 
 typedef struct {
@@ -209,6 +223,24 @@ mcd_status mcd_tune(mcd_ctx *ctx, double dt, int64_t max_events_per_cell, mcd_tu
  * MCD_EINVAL if out of range or if the plan does not fit the GPU's LDS (the
  * previous schedule is kept). */
 mcd_status mcd_set_schedule(mcd_ctx *ctx, int32_t small_max, int32_t grid_per_cu);
+
+/* sigma_d(m, r): dust surface density per particle-mass bin and radius of
+ * the current particles (paper, Benchmark: the run's output is the dust
+ * surface density as a function of particle mass and distance from the
+ * star).
+ * r_edges [n_rb+1], m_edges [n_mb+1]: host arrays, finite and strictly
+ * increasing (r_edges[0] >= 0), copied before the call returns.
+ * sigma [n_rb*n_mb]: device FP64, radius-major; bin (k, l) holds the swarm
+ * masses M of the active particles with r_edges[k] <= r < r_edges[k+1] and
+ * m_edges[l] <= m < m_edges[l+1], divided by the annulus area
+ * pi (r_edges[k+1]^2 - r_edges[k]^2) (area 1 in column mode, where M is per
+ * unit area): g/cm^2 per mass bin.  count [n_rb*n_mb]: device uint32, the
+ * representative particles per bin, or NULL.  Async on the context stream.
+ * The FP64 sums follow the order of device atomics (results may differ by
+ * a relative count * 2^-52 between runs).  MCD_EINVAL on bad edges or
+ * n_rb * n_mb outside [1, 2^24]. */
+mcd_status mcd_sigma_hist(mcd_ctx *ctx, const double *r_edges, int32_t n_rb, const double *m_edges,
+                          int32_t n_mb, double *sigma, uint32_t *count);
 
 /* Copy the counters to the host (synchronises) and report the sticky
  * device flag as MCD_EDEVICE. */

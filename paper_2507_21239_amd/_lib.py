@@ -27,7 +27,7 @@ GEOM_FIELDS = 5
 
 # every function declared in include/mcd.h
 EXPORTS = ("mcd_init", "mcd_bin", "mcd_rates", "mcd_step", "mcd_tune", "mcd_set_schedule",
-           "mcd_get_stats", "mcd_get_cells", "mcd_set_event_log", "mcd_philox", "mcd_last_error",
+           "mcd_sigma_hist", "mcd_get_stats", "mcd_get_cells", "mcd_set_event_log", "mcd_philox", "mcd_last_error",
            "mcd_free")
 
 
@@ -37,7 +37,11 @@ class Params(C.Structure):
         "mu", "m_star", "r_ref", "dm_max", "erosion_chi", "r_in", "r_col", "k0")] + [
         ("kernel", C.c_int32), ("n_r", C.c_int32), ("n_z", C.c_int32), ("column", C.c_int32),
         ("flags", C.c_uint32), ("n_comp", C.c_int32), ("seed", C.c_uint64),
-        ("precision", C.c_int32), ("schedule", C.c_int32)]
+        ("precision", C.c_int32), ("schedule", C.c_int32), ("frag_mode", C.c_int32),
+        ("pad", C.c_int32), ("frag_width", C.c_double)]
+
+
+FRAG_MODES = {"sharp": 0, "ramp": 1, "maxwell": 2}
 
 
 class Particles(C.Structure):
@@ -81,6 +85,7 @@ def load() -> C.CDLL:
         "mcd_step": (i32, [vp, C.c_double, i64, i32]),
         "mcd_tune": (i32, [vp, C.c_double, i64, C.POINTER(TuneResult)]),
         "mcd_set_schedule": (i32, [vp, i32, i32]),
+        "mcd_sigma_hist": (i32, [vp, vp, i32, vp, i32, vp, vp]),
         "mcd_get_stats": (i32, [vp, C.POINTER(Stats)]),
         "mcd_get_cells": (i32, [vp, vp, vp, vp, vp]),
         "mcd_set_event_log": (i32, [vp, vp, i64]),
@@ -108,6 +113,13 @@ def make_params(d: dict, precision: str = "mixed", schedule: str = "batched") ->
             p.precision = PRECISIONS[precision]
         elif name == "schedule":
             p.schedule = SCHEDULES[schedule]
+        elif name == "frag_mode":
+            fm = d.get("frag_mode", "sharp")
+            p.frag_mode = FRAG_MODES[fm] if isinstance(fm, str) else int(fm)
+        elif name == "frag_width":
+            p.frag_width = d.get("frag_width", 0.0)
+        elif name == "pad":
+            pass
         else:
             setattr(p, name, d[name])
     return p

@@ -90,6 +90,20 @@ class Simulation:
         self._check(self.lib.mcd_set_schedule(self.ctx, int(small_max), int(grid_per_cu)),
                     "mcd_set_schedule")
 
+    def sigma_hist(self, r_edges, m_edges) -> tuple[torch.Tensor, torch.Tensor]:
+        """sigma_d(m, r) [n_rb, n_mb] (g/cm^2 per mass bin) and particle counts
+        of the current particles over the given bin edges."""
+        import numpy as np
+        re = np.ascontiguousarray(r_edges, dtype=np.float64)
+        me = np.ascontiguousarray(m_edges, dtype=np.float64)
+        nr, nm = len(re) - 1, len(me) - 1
+        dev = self.t["m"].device
+        sigma = torch.empty((max(nr, 1), max(nm, 1)), dtype=torch.float64, device=dev)
+        count = torch.empty((max(nr, 1), max(nm, 1)), dtype=torch.int32, device=dev)
+        self._check(self.lib.mcd_sigma_hist(self.ctx, re.ctypes.data, nr, me.ctypes.data, nm,
+                                            sigma.data_ptr(), count.data_ptr()), "mcd_sigma_hist")
+        return sigma, count
+
     def rates(self, cell: int, n: int) -> tuple[torch.Tensor, torch.Tensor]:
         out = torch.empty((max(n, 1), max(n, 1)), dtype=torch.float64, device=self.t["m"].device)
         rs = torch.empty(max(n, 1), dtype=torch.float64, device=self.t["m"].device)

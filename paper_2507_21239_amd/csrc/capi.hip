@@ -44,6 +44,9 @@ struct mcd_ctx {
   int grid_per_cu = 0;
   int cus = 0;
   std::vector<int32_t> sizes;  // particle count of every cell of the grid
+  std::vector<double> h_edges;  // histogram bin edges (host copy, read by the async upload)
+  double *d_edges = nullptr;
+  size_t edges_cap = 0;
   double *d_mbak = nullptr;    // tuning backups of m, comp and the device state
   float *d_cbak = nullptr;
   DevState *d_sbak = nullptr;
@@ -111,6 +114,10 @@ std::string check_params(const mcd_params &p) {
   if (p.n_comp < 0 || p.n_comp > MCD_MAX_COMP) return "n_comp must be in [0, 8]";
   if (p.precision != MCD_FP64 && p.precision != MCD_MIXED) return "unknown precision";
   if (p.schedule != MCD_SCHED_PLAIN && p.schedule != MCD_SCHED_BATCHED) return "unknown schedule";
+  if (p.frag_mode != MCD_FRAG_SHARP && p.frag_mode != MCD_FRAG_RAMP && p.frag_mode != MCD_FRAG_MAXWELL)
+    return "unknown frag_mode";
+  if (p.frag_mode == MCD_FRAG_RAMP && !(p.frag_width > 0.0 && p.frag_width <= 1.0))
+    return "frag_width must be in (0, 1] for the ramp";
   return "";
 }
 
@@ -137,6 +144,8 @@ Model make_model(const mcd_params &p) {
   m.kernel = p.kernel;
   m.column = p.column;
   m.n_comp = p.n_comp;
+  m.frag_mode = p.frag_mode;
+  m.frag_width = p.frag_width;
   m.key0 = (uint32_t)p.seed;
   m.key1 = (uint32_t)(p.seed >> 32);
   return m;
@@ -600,6 +609,42 @@ mcd_status mcd_tune(mcd_ctx *c, double dt, int64_t max_events, mcd_tune_result *
   return MCD_OK;
 }
 
+mcd_status mcd_sigma_hist(mcd_ctx *c, const double *r_edges, int32_t n_rb, const double *m_edges,
+                          int32_t n_mb, double *sigma, uint32_t *count) {
+  if (!c) return MCD_EINVAL;
+  if (!r_edges || !m_edges || !sigma || n_rb < 1 || n_mb < 1 ||
+      (int64_t)n_rb * n_mb > ((int64_t)1 << 24))
+    return fail(c, MCD_EINVAL, "sigma_hist needs edges, an output and 1 <= n_rb * n_mb <= 2^24");
+  auto increasing = [](const double *e, int32_t n) {
+    for (int32_t k = 0; k <= n; ++k) {
+      if (!std::isfinite(e[k])) return false;
+      if (k > 0 && !(e[k] > e[k - 1])) return false;
+    }
+    return true;
+  };
+  if (!increasing(r_edges, n_rb) || !increasing(m_edges, n_mb) || r_edges[0] < 0.0)
+    return fail(c, MCD_EINVAL, "bin edges must be finite and strictly increasing, r_edges[0] >= 0");
+  const size_t ne = (size_t)n_rb + 1 + (size_t)n_mb + 1;
+  if (ne > c->edges_cap) {
+    dfree(c->d_edges);
+    c->d_edges = nullptr;
+    c->edges_cap = 0;
+    if (dalloc(&c->d_edges, ne) != hipSuccess)
+      return fail(c, MCD_ENOMEM, "device allocation of the bin edges failed");
+    c->edges_cap = ne;
+  }
+  c->h_edges.assign(r_edges, r_edges + n_rb + 1);
+  c->h_edges.insert(c->h_edges.end(), m_edges, m_edges + n_mb + 1);
+  MCD_HIP(c, hipMemcpyAsync(c->d_edges, c->h_edges.data(), ne * sizeof(double),
+                            hipMemcpyHostToDevice, c->stream));
+  const double *re = c->d_edges, *me = c->d_edges + n_rb + 1;
+  hipError_t e = launch_sigma_hist(c->part.r, c->part.m, c->part.M, c->part.active, c->part.n, re,
+                                   n_rb, me, n_mb, c->prm.column ? 1 : 0, sigma, count, c->cus,
+                                   c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "sigma_hist");
+  return MCD_OK;
+}
+
 mcd_status mcd_get_stats(mcd_ctx *c, mcd_stats *o) {
   if (!c || !o) return MCD_EINVAL;
   DevState s{};
@@ -674,6 +719,7 @@ void mcd_free(mcd_ctx *c) {
   free_grid(c);
   BinBuffers &b = c->bb;
   free_binning(b);
+  dfree(c->d_edges);
   dfree(c->d_mbak);
   dfree(c->d_cbak);
   dfree(c->d_sbak);

@@ -310,11 +310,21 @@ __device__ inline Cand team_pick(Team &tm, double incl, double part, const VT *v
 // The writer also applies the side effects: the anomaly flag and the
 // mass-weighted composition of i on sticking or fragmentation (lanes below
 // n_comp, one component each).
-template <typename RT>
+// PROB: the probabilistic fragmentation criteria (a kernel variant of its
+// own, so that the sharp criterion carries none of their FP64 special
+// functions); their uniform comes from Philox (e, cell, step, 3)
+template <typename RT, bool PROB>
 __device__ inline int event_outcome(const CollideArgs &A, const TeamScratch *S, double mi,
                                     double mj, double Mi, RT dvj, double u4, int gi, int gj,
-                                    int lane, bool writer, double &mnew, Rec<RT> &rin) {
-  const bool fast = !(dvj < (RT)A.P.v_frag);
+                                    int lane, bool writer, uint32_t e, uint32_t cell,
+                                    uint32_t step, double &mnew, Rec<RT> &rin) {
+  bool fast;
+  if constexpr (PROB) {
+    const U4 w = philox4x32_10(U4{e, cell, step, 3u}, A.P.key0, A.P.key1);
+    fast = u01(w.x, w.y) < frag_probability(A.P, (double)dvj);
+  } else {
+    fast = !(dvj < (RT)A.P.v_frag);
+  }
   const int oc = outcome(A.P, fast, mi, mj, u4, mnew);
   if (writer) {
     if ((!(mnew > 0.0) || !isfinite(mnew)) && lane == 0) atomicOr(&A.state->flags, FLAG_BAD_MASS);
@@ -341,7 +351,7 @@ __device__ inline void log_event(const CollideArgs &A, int cell, int64_t e, int 
   }
 }
 
-template <typename RT, int KMAX, bool FAST>
+template <typename RT, int KMAX, bool FAST, bool PROB>
 __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap, int nw, int wave,
                              int lane, uint32_t step) {
   const int s0 = A.cell_start[cell];
@@ -535,8 +545,8 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
                                     m64, dvv, gix);
     double mnew = 0.0;
     Rec<RT> rin;
-    const int oc = event_outcome<RT>(A, tm.S, mi, cj.p0, Mi, (RT)cj.p1, readlane_d(uu4, rl), gi,
-                                     cj.gi, lane, wave == 0, mnew, rin);
+    const int oc = event_outcome<RT, PROB>(A, tm.S, mi, cj.p0, Mi, (RT)cj.p1, readlane_d(uu4, rl), gi,
+                                     cj.gi, lane, wave == 0, (uint32_t)e, c32, step, mnew, rin);
     if (tl == 0) log_event(A, cell, e, i_local, cj.lane * K + cj.q, oc);
     // the owner of i keeps the new mass and record; it alone reads the slot
     // until the next exchange
@@ -602,7 +612,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
 // on four-wave teams (largest first), then small cells on single waves
 // (largest first), each wave popping its own work
 // ---------------------------------------------------------------------------
-template <typename RT, int KMAX, bool FAST>
+template <typename RT, int KMAX, bool FAST, bool PROB>
 __global__ __launch_bounds__(256, sizeof(RT) == 4 ? 3 : 2) void collide_batched(CollideArgs A) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_item;
@@ -630,16 +640,16 @@ __global__ __launch_bounds__(256, sizeof(RT) == 4 ? 3 : 2) void collide_batched(
       cell = A.small_list[item];
     }
     char *base = nw == 4 ? smem : smem + (size_t)wave * small_bytes;
-    process_cell<RT, KMAX, FAST>(A, cell, base, nw == 4 ? A.big_cap : A.small_cap, nw,
+    process_cell<RT, KMAX, FAST, PROB>(A, cell, base, nw == 4 ? A.big_cap : A.small_cap, nw,
                                  nw == 4 ? wave : 0, lane, step);
   }
 }
 
 // plain schedule: one four-wave workgroup per cell, cells in index order
-template <typename RT, int KMAX, bool FAST>
+template <typename RT, int KMAX, bool FAST, bool PROB>
 __global__ __launch_bounds__(256) void collide_plain(CollideArgs A) {
   extern __shared__ __align__(16) char smem[];
-  process_cell<RT, KMAX, FAST>(A, blockIdx.x, smem, A.big_cap, 4, threadIdx.x >> 6, threadIdx.x & 63,
+  process_cell<RT, KMAX, FAST, PROB>(A, blockIdx.x, smem, A.big_cap, 4, threadIdx.x >> 6, threadIdx.x & 63,
                          A.state->step);
 }
 
@@ -696,10 +706,10 @@ static hipError_t prepare(Kern kern, size_t lds) {
   return hipSuccess;
 }
 
-template <typename RT, int KMAX, bool FAST>
+template <typename RT, int KMAX, bool FAST, bool PROB>
 static hipError_t run_batched(const CollideArgs &a, int grid_override, hipStream_t s) {
   const size_t lds = std::max(region_bytes<RT>(a.big_cap, 4), 4 * region_bytes<RT>(a.small_cap, 1));
-  auto kern = collide_batched<RT, KMAX, FAST>;
+  auto kern = collide_batched<RT, KMAX, FAST, PROB>;
   hipError_t e = prepare(kern, lds);
   int dev = 0, cus = 0, per_cu = 0;
   if (e == hipSuccess) e = hipGetDevice(&dev);
@@ -716,10 +726,10 @@ static hipError_t run_batched(const CollideArgs &a, int grid_override, hipStream
   return hipGetLastError();
 }
 
-template <typename RT, int KMAX, bool FAST>
+template <typename RT, int KMAX, bool FAST, bool PROB>
 static hipError_t run_plain(const CollideArgs &a, int n_cells, hipStream_t s) {
   const size_t lds = region_bytes<RT>(a.big_cap, 4);
-  auto kern = collide_plain<RT, KMAX, FAST>;
+  auto kern = collide_plain<RT, KMAX, FAST, PROB>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
   if (n_cells > 0) kern<<<n_cells, 256, lds, s>>>(a);
@@ -733,6 +743,30 @@ static bool fast_path(const CollideArgs &a, int precision) {
   return precision != 0 && a.P.kernel == K_PHYSICAL && (a.P.flags & all) == all;
 }
 
+template <bool PROB>
+static hipError_t launch_collide_t(const CollideArgs &a, int precision, int schedule, int n_cells,
+                                   bool wide, int grid_override, hipStream_t s) {
+  const bool fast = fast_path(a, precision);
+  if (schedule == 0) {
+    if (precision == 0)
+      return wide ? run_plain<double, 8, false, PROB>(a, n_cells, s)
+                  : run_plain<double, 4, false, PROB>(a, n_cells, s);
+    if (fast)
+      return wide ? run_plain<float, 8, true, PROB>(a, n_cells, s)
+                  : run_plain<float, 4, true, PROB>(a, n_cells, s);
+    return wide ? run_plain<float, 8, false, PROB>(a, n_cells, s)
+                : run_plain<float, 4, false, PROB>(a, n_cells, s);
+  }
+  if (precision == 0)
+    return wide ? run_batched<double, 8, false, PROB>(a, grid_override, s)
+                : run_batched<double, 4, false, PROB>(a, grid_override, s);
+  if (fast)
+    return wide ? run_batched<float, 8, true, PROB>(a, grid_override, s)
+                : run_batched<float, 4, true, PROB>(a, grid_override, s);
+  return wide ? run_batched<float, 8, false, PROB>(a, grid_override, s)
+              : run_batched<float, 4, false, PROB>(a, grid_override, s);
+}
+
 hipError_t launch_collide(const CollideArgs &a, int precision, int schedule, int n_cells,
                           int max_cell, int grid_override, hipStream_t s) {
   // slots per lane: four-wave teams hold big_cap particles, single waves
@@ -741,25 +775,10 @@ hipError_t launch_collide(const CollideArgs &a, int precision, int schedule, int
   const int kneed = schedule == 0 ? std::max(k_big, (max_cell + 255) / 256) : std::max(k_big, k_small);
   if (kneed > 8) return hipErrorInvalidValue;
   const bool wide = kneed > 4;
-  const bool fast = fast_path(a, precision);
-  if (schedule == 0) {
-    if (precision == 0)
-      return wide ? run_plain<double, 8, false>(a, n_cells, s)
-                  : run_plain<double, 4, false>(a, n_cells, s);
-    if (fast)
-      return wide ? run_plain<float, 8, true>(a, n_cells, s)
-                  : run_plain<float, 4, true>(a, n_cells, s);
-    return wide ? run_plain<float, 8, false>(a, n_cells, s)
-                : run_plain<float, 4, false>(a, n_cells, s);
-  }
-  if (precision == 0)
-    return wide ? run_batched<double, 8, false>(a, grid_override, s)
-                : run_batched<double, 4, false>(a, grid_override, s);
-  if (fast)
-    return wide ? run_batched<float, 8, true>(a, grid_override, s)
-                : run_batched<float, 4, true>(a, grid_override, s);
-  return wide ? run_batched<float, 8, false>(a, grid_override, s)
-              : run_batched<float, 4, false>(a, grid_override, s);
+  // the probabilistic fragmentation criteria apply only to the physical kernel
+  const bool prob = a.P.frag_mode != FRAG_SHARP && a.P.kernel == K_PHYSICAL;
+  return prob ? launch_collide_t<true>(a, precision, schedule, n_cells, wide, grid_override, s)
+              : launch_collide_t<false>(a, precision, schedule, n_cells, wide, grid_override, s);
 }
 
 hipError_t launch_rates_cell(const CollideArgs &a, int precision, int cell, double *r_out,

@@ -116,6 +116,12 @@ struct BinBuffers {
   int64_t cap;         // particles
   int32_t tiles;
 };
+// sigma_d(m, r) histogram of the particles (diagnostics.hip)
+hipError_t launch_sigma_hist(const double *r, const double *m, const double *M,
+                             const uint8_t *active, int64_t N, const double *re, int n_rb,
+                             const double *me, int n_mb, int column, double *sigma,
+                             uint32_t *count, int cus, hipStream_t s);
+
 hipError_t launch_binning(const Model &P, int n_r, int n_z, const double *r, const double *z,
                           const uint8_t *active, int64_t N, BinBuffers &b, int32_t *cell_start,
                           int32_t *order, double *geom, double *gas, DevState *state,

@@ -44,11 +44,13 @@ enum { OUT_STICK = 0, OUT_ERODE = 1, OUT_ERODED_SMALL = 2, OUT_FRAG = 3 };
 // model constants copied to the device by value
 struct Model {
   double sigma_g0, T0, p, q, alpha, v_frag, erosion_ratio, rho_s, mu, m_star, r_ref;
-  double dm_max, erosion_chi, r_in, r_col, k0, m0;
+  double dm_max, erosion_chi, r_in, r_col, k0, m0, frag_width;
   uint32_t flags;
-  int32_t kernel, column, n_comp;
+  int32_t kernel, column, n_comp, frag_mode;
   uint32_t key0, key1;
 };
+
+enum : int32_t { FRAG_SHARP = 0, FRAG_RAMP = 1, FRAG_MAXWELL = 2 };
 
 // gas state of a cell, from its six primaries (V, rho_g, T, alpha, r_c,
 // zeta = z_c / H)
@@ -363,6 +365,26 @@ __host__ __device__ inline double frag_draw(double lo, double hi, double u) {
   const double x = slo + u * (shi - slo);
   const double x2 = x * x;
   return x2 * x2 * x2;
+}
+
+// probability that a collision at mean relative velocity dv fragments (or
+// erodes): linear ramp from (1 - w) v_frag to v_frag, or the tail above
+// v_frag of the Maxwell speed distribution with mean dv (scale a =
+// dv sqrt(pi/8)): erfc(x) + 2/sqrt(pi) x exp(-x^2), x = v_frag / (sqrt(2) a)
+__host__ __device__ inline double frag_probability(const Model &P, double dv) {
+  const double vf = P.v_frag;
+  if (P.frag_mode == FRAG_RAMP) {
+    const double lo = (1.0 - P.frag_width) * vf;
+    if (dv <= lo) return 0.0;
+    if (dv >= vf) return 1.0;
+    return (dv - lo) / (vf - lo);
+  }
+  if (P.frag_mode == FRAG_MAXWELL) {
+    if (!(dv > 0.0)) return 0.0;
+    const double x = 2.0 * vf / (sqrt(kPi) * dv);
+    return erfc(x) + 2.0 / sqrt(kPi) * x * exp(-x * x);
+  }
+  return dv < vf ? 0.0 : 1.0;
 }
 
 // grouping factor max(1, dm_max m_i / m_j)
