@@ -242,6 +242,31 @@ mcd_status mcd_set_schedule(mcd_ctx *ctx, int32_t small_max, int32_t grid_per_cu
 mcd_status mcd_sigma_hist(mcd_ctx *ctx, const double *r_edges, int32_t n_rb, const double *m_edges,
                           int32_t n_mb, double *sigma, uint32_t *count);
 
+/* Particle histories (the paper's Statement of Need: a Lagrangian method
+ * follows the histories of its particles and their compositions).  A
+ * snapshot is the state of the chosen fields at its place in the context
+ * stream: their device copy is queued there (so it sees every step queued
+ * before, and no later one), and the copy to host_dst runs on a separate
+ * stream while later steps proceed.  host_dst must stay valid until
+ * mcd_snapshot_wait returns; pinned host memory (hipHostMalloc) makes the
+ * transfer asynchronous.  Layout: the chosen fields in the order r, z, m
+ * (FP64 [N] each), active (uint8 [N]), comp (FP32 [n_comp][N]), each padded
+ * to a multiple of 16 bytes (mcd_snapshot_bytes gives the total).  Two
+ * snapshots can be in flight; a third waits, in stream order, for the
+ * oldest transfer.  *ticket (may be NULL) numbers the snapshot for
+ * mcd_snapshot_wait. */
+#define MCD_SNAP_R 1u
+#define MCD_SNAP_Z 2u
+#define MCD_SNAP_M 4u
+#define MCD_SNAP_ACTIVE 8u
+#define MCD_SNAP_COMP 16u
+#define MCD_SNAP_ALL 31u
+mcd_status mcd_snapshot_bytes(mcd_ctx *ctx, uint32_t fields, size_t *bytes);
+mcd_status mcd_snapshot(mcd_ctx *ctx, uint32_t fields, void *host_dst, size_t bytes,
+                        int64_t *ticket);
+/* Block until the snapshot with this ticket is in host memory. */
+mcd_status mcd_snapshot_wait(mcd_ctx *ctx, int64_t ticket);
+
 /* Copy the counters to the host (synchronises) and report the sticky
  * device flag as MCD_EDEVICE. */
 mcd_status mcd_get_stats(mcd_ctx *ctx, mcd_stats *host_out);

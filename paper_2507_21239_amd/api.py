@@ -104,6 +104,23 @@ class Simulation:
                                             sigma.data_ptr(), count.data_ptr()), "mcd_sigma_hist")
         return sigma, count
 
+    def snapshot(self, fields=("r", "z", "m", "active", "comp"), out: torch.Tensor | None = None):
+        """Queue an asynchronous copy of the current particle state to pinned
+        host memory (`out`, or a new pinned buffer); returns a Snapshot whose
+        wait() gives numpy views of the fields."""
+        fields = tuple(f for f in fields if f != "comp" or self.t.get("comp") is not None)
+        bits = sum(_lib.SNAP_FIELDS[f] for f in fields)
+        nbytes = C.c_size_t()
+        self._check(self.lib.mcd_snapshot_bytes(self.ctx, bits, C.byref(nbytes)), "mcd_snapshot_bytes")
+        if out is None:
+            out = torch.empty(nbytes.value, dtype=torch.uint8, pin_memory=True)
+        if out.device.type != "cpu" or out.numel() * out.element_size() < nbytes.value:
+            raise ValueError("snapshot buffer must be host memory of at least %d bytes" % nbytes.value)
+        ticket = C.c_int64()
+        self._check(self.lib.mcd_snapshot(self.ctx, bits, out.data_ptr(), nbytes.value,
+                                          C.byref(ticket)), "mcd_snapshot")
+        return Snapshot(self, ticket.value, out, fields)
+
     def rates(self, cell: int, n: int) -> tuple[torch.Tensor, torch.Tensor]:
         out = torch.empty((max(n, 1), max(n, 1)), dtype=torch.float64, device=self.t["m"].device)
         rs = torch.empty(max(n, 1), dtype=torch.float64, device=self.t["m"].device)
@@ -153,6 +170,32 @@ class Simulation:
             self.close()
         except Exception:
             pass
+
+
+class Snapshot:
+    """A queued particle snapshot (see Simulation.snapshot)."""
+
+    def __init__(self, sim: Simulation, ticket: int, buf: torch.Tensor, fields: tuple):
+        self.sim, self.ticket, self.buf, self.fields = sim, ticket, buf, fields
+
+    def wait(self) -> dict:
+        import numpy as np
+        self.sim._check(self.sim.lib.mcd_snapshot_wait(self.sim.ctx, self.ticket), "mcd_snapshot_wait")
+        raw = self.buf.numpy().view(np.uint8)
+        n = self.sim.N
+        nc = int(self.sim.params.get("n_comp", 0)) if "comp" in self.fields else 0
+        sizes = dict(r=(np.float64, n), z=(np.float64, n), m=(np.float64, n),
+                     active=(np.uint8, n), comp=(np.float32, nc * n))
+        out, off = {}, 0
+        for f in ("r", "z", "m", "active", "comp"):
+            if f not in self.fields:
+                continue
+            dt, cnt = sizes[f]
+            nb = np.dtype(dt).itemsize * cnt
+            a = raw[off:off + nb].view(dt)
+            out[f] = a.reshape(nc, n) if f == "comp" else a
+            off += (nb + 15) // 16 * 16
+        return out
 
 
 def philox(ctr: torch.Tensor, key: int, stream=None) -> torch.Tensor:

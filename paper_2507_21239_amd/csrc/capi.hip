@@ -44,6 +44,14 @@ struct mcd_ctx {
   int grid_per_cu = 0;
   int cus = 0;
   std::vector<int32_t> sizes;  // particle count of every cell of the grid
+  // snapshots: two device staging buffers filled in stream order, each
+  // copied to the caller's host memory on copy_stream
+  hipStream_t copy_stream = nullptr;
+  char *d_stage[2] = {nullptr, nullptr};
+  size_t stage_cap = 0;
+  hipEvent_t ev_staged[2] = {nullptr, nullptr}, ev_landed[2] = {nullptr, nullptr};
+  bool slot_used[2] = {false, false};
+  int64_t snap_count = 0;
   std::vector<double> h_edges;  // histogram bin edges (host copy, read by the async upload)
   double *d_edges = nullptr;
   size_t edges_cap = 0;
@@ -645,6 +653,91 @@ mcd_status mcd_sigma_hist(mcd_ctx *c, const double *r_edges, int32_t n_rb, const
   return MCD_OK;
 }
 
+// bytes of a snapshot of the given fields, each field padded to 16 bytes:
+// r, z, m (8 N each), active (N), comp (4 n_comp N), in that order
+static size_t snapshot_layout(const mcd_ctx *c, uint32_t fields, size_t off[5]) {
+  const size_t N = (size_t)c->part.n;
+  const size_t sz[5] = {8 * N, 8 * N, 8 * N, N,
+                        c->part.comp ? 4 * (size_t)c->prm.n_comp * N : 0};
+  size_t total = 0;
+  for (int f = 0; f < 5; ++f) {
+    off[f] = total;
+    if (fields & (1u << f)) total += (sz[f] + 15) / 16 * 16;
+  }
+  return total;
+}
+
+mcd_status mcd_snapshot_bytes(mcd_ctx *c, uint32_t fields, size_t *bytes) {
+  if (!c || !bytes) return MCD_EINVAL;
+  if (fields == 0 || (fields & ~(uint32_t)MCD_SNAP_ALL))
+    return fail(c, MCD_EINVAL, "snapshot fields must be a nonzero set of MCD_SNAP_* bits");
+  size_t off[5];
+  *bytes = snapshot_layout(c, fields, off);
+  return MCD_OK;
+}
+
+mcd_status mcd_snapshot(mcd_ctx *c, uint32_t fields, void *host_dst, size_t bytes,
+                        int64_t *ticket) {
+  if (!c) return MCD_EINVAL;
+  if (!host_dst || fields == 0 || (fields & ~(uint32_t)MCD_SNAP_ALL))
+    return fail(c, MCD_EINVAL, "snapshot needs a destination and a nonzero set of MCD_SNAP_* bits");
+  if ((fields & MCD_SNAP_COMP) && !c->part.comp)
+    return fail(c, MCD_EINVAL, "no composition fractions to snapshot");
+  size_t off[5];
+  const size_t total = snapshot_layout(c, fields, off);
+  if (bytes < total) return fail(c, MCD_EINVAL, "snapshot buffer too small");
+  if (!c->copy_stream) {
+    MCD_HIP(c, hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
+    for (int k = 0; k < 2; ++k) {
+      MCD_HIP(c, hipEventCreateWithFlags(&c->ev_staged[k], hipEventDisableTiming));
+      MCD_HIP(c, hipEventCreateWithFlags(&c->ev_landed[k], hipEventDisableTiming));
+    }
+  }
+  if (total > c->stage_cap) {
+    // wait until no transfer reads the old buffers, then grow them
+    MCD_HIP(c, hipStreamSynchronize(c->copy_stream));
+    for (int k = 0; k < 2; ++k) {
+      dfree(c->d_stage[k]);
+      c->d_stage[k] = nullptr;
+    }
+    c->stage_cap = 0;
+    for (int k = 0; k < 2; ++k)
+      if (dalloc(&c->d_stage[k], total) != hipSuccess)
+        return fail(c, MCD_ENOMEM, "device allocation of the snapshot staging failed");
+    c->stage_cap = total;
+    c->slot_used[0] = c->slot_used[1] = false;
+  }
+  const int k = (int)(c->snap_count & 1);
+  // the staging buffer of this slot must have been copied out before reuse
+  if (c->slot_used[k]) MCD_HIP(c, hipStreamWaitEvent(c->stream, c->ev_landed[k], 0));
+  const size_t N = (size_t)c->part.n;
+  const void *src[5] = {c->part.r, c->part.z, c->part.m, c->part.active, c->part.comp};
+  const size_t sz[5] = {8 * N, 8 * N, 8 * N, N,
+                        c->part.comp ? 4 * (size_t)c->prm.n_comp * N : 0};
+  for (int f = 0; f < 5; ++f)
+    if ((fields & (1u << f)) && sz[f])
+      MCD_HIP(c, hipMemcpyAsync(c->d_stage[k] + off[f], src[f], sz[f], hipMemcpyDeviceToDevice,
+                                c->stream));
+  MCD_HIP(c, hipEventRecord(c->ev_staged[k], c->stream));
+  MCD_HIP(c, hipStreamWaitEvent(c->copy_stream, c->ev_staged[k], 0));
+  MCD_HIP(c, hipMemcpyAsync(host_dst, c->d_stage[k], total, hipMemcpyDeviceToHost, c->copy_stream));
+  MCD_HIP(c, hipEventRecord(c->ev_landed[k], c->copy_stream));
+  c->slot_used[k] = true;
+  if (ticket) *ticket = c->snap_count;
+  ++c->snap_count;
+  return MCD_OK;
+}
+
+mcd_status mcd_snapshot_wait(mcd_ctx *c, int64_t ticket) {
+  if (!c) return MCD_EINVAL;
+  if (ticket < 0 || ticket >= c->snap_count)
+    return fail(c, MCD_EINVAL, "unknown snapshot ticket");
+  // transfers land in order on one stream; the slot's event belongs to this
+  // snapshot or to a later one, either way this snapshot has landed after it
+  MCD_HIP(c, hipEventSynchronize(c->ev_landed[ticket & 1]));
+  return MCD_OK;
+}
+
 mcd_status mcd_get_stats(mcd_ctx *c, mcd_stats *o) {
   if (!c || !o) return MCD_EINVAL;
   DevState s{};
@@ -724,6 +817,13 @@ void mcd_free(mcd_ctx *c) {
   dfree(c->d_cbak);
   dfree(c->d_sbak);
   dfree(c->d_state);
+  if (c->copy_stream) (void)hipStreamSynchronize(c->copy_stream);
+  for (int k = 0; k < 2; ++k) {
+    dfree(c->d_stage[k]);
+    if (c->ev_staged[k]) (void)hipEventDestroy(c->ev_staged[k]);
+    if (c->ev_landed[k]) (void)hipEventDestroy(c->ev_landed[k]);
+  }
+  if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }

@@ -21,7 +21,12 @@ import numpy as np
 
 def run(N: int = 100_000, n_r: int = 50, n_z: int = 10, years: float = 1e4, dt_yr: float = 1.0,
         precision: str = "mixed", seed: int = 0, n_comp: int = 0, r_bins: int = 60,
-        m_bins: int = 90, chunk: int = 200, verbose: bool = True) -> dict:
+        m_bins: int = 90, chunk: int = 200, history_every: int = 0, history_ids=None,
+        verbose: bool = True) -> dict:
+    """history_every > 0: every that many steps an asynchronous snapshot of
+    (r, z, m[, comp]) is queued and the rows of history_ids (default: 16
+    particles spread over the disk) are kept: history [n_snap, n_ids, 3 +
+    n_comp]."""
     import torch
 
     from . import api
@@ -33,17 +38,39 @@ def run(N: int = 100_000, n_r: int = 50, n_z: int = 10, years: float = 1e4, dt_y
     sim.bin()
     tuned = sim.tune(dt, 0)
     steps = int(round(years / dt_yr))
+    if history_every > 0:
+        chunk = history_every
+        ids = np.asarray(history_ids if history_ids is not None
+                         else np.linspace(0, N - 1, 16).astype(np.int64))
+    fields = ("r", "z", "m") + (("comp",) if n_comp else ())
+    pending, history = [], []
+
+    def keep(snap):
+        d = snap.wait()
+        row = [d["r"][ids], d["z"][ids], d["m"][ids]] + \
+              ([d["comp"][c][ids] for c in range(n_comp)] if n_comp else [])
+        history.append(np.stack(row, axis=1))
+
     t0 = time.perf_counter()
     done = 0
     while done < steps:
         k = min(chunk, steps - done)
         sim.step(dt, 0, k)
         done += k
+        if history_every > 0:
+            if len(pending) < 2:
+                pending.append(sim.snapshot(fields))
+            else:
+                old = pending.pop(0)
+                keep(old)                 # the older transfer has landed: reuse its buffer
+                pending.append(sim.snapshot(fields, out=old.buf))
         if verbose:
             torch.cuda.synchronize()
             st = sim.stats()
             print(f"[disk_run] {done * dt_yr:.0f} yr  events {st['events']}  active {st['n_active']}  "
                   f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    for snap in pending:
+        keep(snap)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = sim.stats()
@@ -58,6 +85,9 @@ def run(N: int = 100_000, n_r: int = 50, n_z: int = 10, years: float = 1e4, dt_y
                outcomes=list(st["outcomes"]), n_active=int(act.sum().item()),
                active_swarm_mass=float(dev["M"][act].sum().item()), wall_s=wall,
                tuned_schedule=tuned, years=steps * dt_yr)
+    if history_every > 0:
+        out["history"] = np.stack(history) if history else np.zeros((0, len(ids), 3 + n_comp))
+        out["history_ids"] = ids
     sim.close()
     return out
 
@@ -74,10 +104,13 @@ def main(argv=None):
     ap.add_argument("--comp", type=int, default=0, help="composition fractions per particle")
     ap.add_argument("--r-bins", type=int, default=60)
     ap.add_argument("--m-bins", type=int, default=90)
+    ap.add_argument("--history-every", type=int, default=0,
+                    help="record (r, z, m[, comp]) of 16 particles every K steps")
     ap.add_argument("--out", default="sigma_d.npz")
     a = ap.parse_args(argv)
     out = run(N=a.particles, n_r=a.nr, n_z=a.nz, years=a.years, dt_yr=a.dt, precision=a.precision,
-              seed=a.seed, n_comp=a.comp, r_bins=a.r_bins, m_bins=a.m_bins)
+              seed=a.seed, n_comp=a.comp, r_bins=a.r_bins, m_bins=a.m_bins,
+              history_every=a.history_every)
     np.savez(a.out, **{k: np.asarray(v) for k, v in out.items() if k != "tuned_schedule"})
     print(f"[disk_run] {out['years']:.0f} yr in {out['wall_s']:.1f} s, {out['events']} collisions, "
           f"sigma_d written to {a.out}", file=sys.stderr)

@@ -85,7 +85,13 @@ def test_benchmark_shaped_run_conserves_swarm_mass():
     from paper_2507_21239_amd import disk_run
     say("disk_run short")
     out = disk_run.run(N=20_000, n_r=20, n_z=5, years=20.0, dt_yr=1.0, precision="mixed",
-                       r_bins=40, m_bins=50, verbose=False)
+                       r_bins=40, m_bins=50, history_every=4, n_comp=8, verbose=False)
+    # histories: one row per 4 steps, masses never below the monomer mass,
+    # composition fractions summing to one (one-hot start, mass-weighted mixing)
+    h = out["history"]
+    assert h.shape == (5, 16, 3 + 8)
+    assert np.all(h[:, :, 2] > 0.0)
+    assert np.allclose(h[:, :, 3:].sum(axis=2), 1.0, atol=1e-5)
     area = np.pi * (out["r_edges"][1:] ** 2 - out["r_edges"][:-1] ** 2)
     binned = float((out["sigma"] * area[:, None]).sum())
     # every active particle lies inside the edges, which span the initial disk
