@@ -29,7 +29,35 @@ class Params(C.Structure):
         "mu", "m_star", "r_ref", "dm_max", "erosion_chi", "r_in", "r_col", "k0")] + [
         ("kernel", C.c_int32), ("n_r", C.c_int32), ("n_z", C.c_int32), ("column", C.c_int32),
         ("flags", C.c_uint32), ("n_comp", C.c_int32), ("seed", C.c_uint64),
-        ("frag_mode", C.c_int32), ("pad_", C.c_int32), ("frag_width", C.c_double)]
+        ("frag_mode", C.c_int32), ("pad_", C.c_int32), ("frag_width", C.c_double),
+        ("grid", C.c_void_p)]
+
+
+class GasGrid(C.Structure):
+    _fields_ = [("n_r", C.c_int32), ("n_z", C.c_int32)] + [
+        (n, C.POINTER(C.c_double)) for n in ("lr", "zn", "lrho", "lT", "lA", "lS")]
+
+
+class LocalGas(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("rho_g", "T", "alpha", "cs", "Omega", "H", "slopeP", "corr")]
+
+
+def grid_build(gas_grid: dict):
+    """The oracle's gridded gas from node values: dict of r_nodes [n_r],
+    z_nodes [n_z], rho, T, alpha [n_r, n_z].  Returns (GasGrid, arrays kept
+    alive by the caller)."""
+    rn = np.ascontiguousarray(gas_grid["r_nodes"], dtype=np.float64)
+    zn = np.ascontiguousarray(gas_grid["z_nodes"], dtype=np.float64)
+    nr, nz = len(rn), len(zn)
+    rho, T, A = (np.ascontiguousarray(gas_grid[k], dtype=np.float64).reshape(nr, nz)
+                 for k in ("rho", "T", "alpha"))
+    out = dict(lr=np.zeros(nr), zn=np.zeros(nz), lrho=np.zeros((nr, nz)), lT=np.zeros((nr, nz)),
+               lA=np.zeros((nr, nz)), lS=np.zeros(nr))
+    lib().orc_grid_fill(nr, nz, _ptr(rn, C.c_double), _ptr(zn, C.c_double), _ptr(rho, C.c_double),
+                        _ptr(T, C.c_double), _ptr(A, C.c_double),
+                        *[_ptr(out[k], C.c_double) for k in ("lr", "zn", "lrho", "lT", "lA", "lS")])
+    g = GasGrid(nr, nz, *[_ptr(out[k], C.c_double) for k in ("lr", "zn", "lrho", "lT", "lA", "lS")])
+    return g, out
 
 
 FRAG_MODES = {"sharp": 0, "ramp": 1, "maxwell": 2}
@@ -94,6 +122,8 @@ def lib():
             "orc_transport": (None, [P, C.c_int64, dp, dp, dp, u8p, C.c_uint32, C.c_double]),
             "orc_collide_all": (None, [P, C.c_int32, ip, ip, dp, C.c_uint32, dp, dp, fp, C.c_int64,
                                        C.c_double, C.c_int64, vp, C.c_int64, vp, C.c_int32]),
+            "orc_grid_fill": (None, [C.c_int32, C.c_int32] + [dp] * 11),
+            "orc_local_gas_at": (None, [P, C.c_double, C.c_double, vp]),
             "orc_sigma_hist": (C.c_int64, [C.c_int64, dp, dp, dp, u8p, dp, C.c_int32, dp, C.c_int32,
                                            C.c_int32, dp, C.POINTER(C.c_uint32)]),
         }
@@ -124,6 +154,13 @@ def make_params(d: dict) -> Params:
             p.frag_width = d.get("frag_width", 0.0)
         elif name == "pad_":
             pass
+        elif name == "grid":
+            if d.get("gas_grid") is not None:
+                g, keep = grid_build(d["gas_grid"])
+                p._grid = (g, keep)          # alive as long as the Params object
+                p.grid = C.cast(C.pointer(g), C.c_void_p)
+            else:
+                p.grid = None
         else:
             setattr(p, name, d[name])
     return p
@@ -260,6 +297,13 @@ def transport(params: dict, part: dict, step: int, dt: float) -> None:
     assert act.dtype == np.uint8
     lib().orc_transport(C.byref(make_params(params)), len(r), _ptr(r, C.c_double), _ptr(z, C.c_double),
                         _ptr(m, C.c_double), _ptr(act, C.c_uint8), step, dt)
+
+
+def local_gas(params: dict, r: float, z: float) -> dict:
+    o = LocalGas()
+    prm = make_params(params)
+    lib().orc_local_gas_at(C.byref(prm), r, z, C.byref(o))
+    return {n: getattr(o, n) for n, _ in LocalGas._fields_}
 
 
 def sigma_hist(part: dict, r_edges, m_edges, column: bool = False) -> tuple:

@@ -95,6 +95,78 @@ void orc_disk_local(const orc_params *P, double r, double z, double *Sigma_g, do
   *rho_g = (*Sigma_g) / (sqrt(2.0 * PI) * (*H)) * exp(-(z * z) / (2.0 * (*H) * (*H)));
 }
 
+/* ------------------------------------------------------------------------
+ * gas at a point: the power-law disk, or the gridded gas
+ * ------------------------------------------------------------------------ */
+void orc_grid_fill(int32_t n_r, int32_t n_z, const double *r_nodes, const double *z_nodes,
+                   const double *rho, const double *T, const double *alpha, double *lr, double *zn,
+                   double *lrho, double *lT, double *lA, double *lS) {
+  for (int32_t k = 0; k < n_r; ++k) lr[k] = log(r_nodes[k]);
+  for (int32_t l = 0; l < n_z; ++l) zn[l] = z_nodes[l];
+  for (int32_t k = 0; k < n_r; ++k) {
+    double col = z_nodes[0] * rho[(int64_t)k * n_z];  /* below the first node */
+    for (int32_t l = 0; l < n_z; ++l) {
+      const int64_t i = (int64_t)k * n_z + l;
+      lrho[i] = log(rho[i]);
+      lT[i] = log(T[i]);
+      lA[i] = log(alpha[i]);
+      if (l + 1 < n_z) col += (z_nodes[l + 1] - z_nodes[l]) * (rho[i] + rho[i + 1]) / 2.0;
+    }
+    lS[k] = log(2.0 * col); /* both halves of the disk */
+  }
+}
+
+/* cell of a node array containing x (clamped to the first / last cell) and
+ * the fractional position inside it (0 or 1 outside the nodes) */
+static void orc_locate(const double *nodes, int32_t n, double x, int32_t *k, double *w) {
+  if (!(x > nodes[0])) { *k = 0; *w = 0.0; return; }
+  if (!(x < nodes[n - 1])) { *k = n - 2; *w = 1.0; return; }
+  int32_t lo = 0, hi = n - 1; /* nodes[lo] <= x < nodes[hi] */
+  while (hi - lo > 1) {
+    const int32_t mid = lo + (hi - lo) / 2;
+    if (x < nodes[mid]) hi = mid; else lo = mid;
+  }
+  *k = lo;
+  *w = (x - nodes[lo]) / (nodes[lo + 1] - nodes[lo]);
+}
+
+void orc_local_gas_at(const orc_params *P, double r, double z, orc_local_gas *o) {
+  const orc_gas_grid *G = P->grid;
+  if (!G) {
+    double Sg;
+    orc_disk_local(P, r, z, &Sg, &o->T, &o->cs, &o->Omega, &o->H, &o->rho_g);
+    o->alpha = P->alpha;
+    o->slopeP = P->p + (P->q + 3.0) / 2.0;
+    o->corr = 1.5 - P->q - P->p;
+    return;
+  }
+  /* bilinear in (ln r, z) of ln rho_g, ln T, ln alpha; r-slopes of the same
+   * interpolants at this height */
+  int32_t k, l;
+  double wx, wz;
+  orc_locate(G->lr, G->n_r, log(r), &k, &wx);
+  orc_locate(G->zn, G->n_z, z, &l, &wz);
+  const int64_t i00 = (int64_t)k * G->n_z + l, i10 = i00 + G->n_z, i01 = i00 + 1, i11 = i10 + 1;
+  const double dx = G->lr[k + 1] - G->lr[k];
+  const double *f[3] = {G->lrho, G->lT, G->lA};
+  double val[3], slope[3];
+  for (int q = 0; q < 3; ++q) {
+    const double *a = f[q];
+    val[q] = (1.0 - wx) * (1.0 - wz) * a[i00] + wx * (1.0 - wz) * a[i10] +
+             (1.0 - wx) * wz * a[i01] + wx * wz * a[i11];
+    slope[q] = ((1.0 - wz) * (a[i10] - a[i00]) + wz * (a[i11] - a[i01])) / dx;
+  }
+  o->rho_g = exp(val[0]);
+  o->T = exp(val[1]);
+  o->alpha = exp(val[2]);
+  o->cs = sqrt(KB * o->T / (P->mu * MH));
+  o->Omega = sqrt(GRAV * P->m_star / (r * r * r));
+  o->H = o->cs / o->Omega;
+  o->slopeP = -(slope[0] + slope[1]); /* pressure rho_g c_s^2 ~ rho_g T */
+  const double dlnS = (G->lS[k + 1] - G->lS[k]) / dx;
+  o->corr = dlnS + slope[2] + slope[1] + 1.5;
+}
+
 /* derived gas state of a cell from its six primaries (V, rho_g, T, alpha,
  * r_c, zeta = z_c/H).  Mean free path of H2, molecular viscosity, Reynolds
  * number and the large-eddy velocity follow Ormel & Cuzzi (2007); the
@@ -110,7 +182,13 @@ void orc_gas_derive(const orc_params *P, const double prim[ORC_GAS_FIELDS], orc_
   g->Omega = sqrt(GRAV * P->m_star / (g->r_c * g->r_c * g->r_c));
   g->H = g->cs / g->Omega;
   g->z_c = g->zeta * g->H;
-  g->eta_vK = 0.5 * (g->cs * g->cs) / (g->Omega * g->r_c) * (P->p + (P->q + 3.0) / 2.0);
+  if (P->grid) { /* pressure slope of the gridded gas at the cell centre */
+    orc_local_gas lg;
+    orc_local_gas_at(P, g->r_c, g->z_c, &lg);
+    g->eta_vK = 0.5 * (g->cs * g->cs) / (g->Omega * g->r_c) * lg.slopeP;
+  } else {
+    g->eta_vK = 0.5 * (g->cs * g->cs) / (g->Omega * g->r_c) * (P->p + (P->q + 3.0) / 2.0);
+  }
   g->v_th = sqrt(8.0 / PI) * g->cs;
   g->lambda = P->mu * MH / (g->rho_g * SIGMA_H2);
   g->nu = 0.5 * g->v_th * g->lambda;
@@ -381,9 +459,9 @@ int64_t orc_bin(const orc_params *P, int64_t N, const double *r, const double *z
       gm[0] = r_lo; gm[1] = r_hi; gm[2] = z_lo; gm[3] = z_hi; gm[4] = V;
       double *gs = gas + (int64_t)c * ORC_GAS_FIELDS;
       if (s1 > s0) {
-        double Sg, T, cs, Om, H, rho;
-        orc_disk_local(P, r_c, z_c, &Sg, &T, &cs, &Om, &H, &rho);
-        gs[0] = V; gs[1] = rho; gs[2] = T; gs[3] = P->alpha; gs[4] = r_c; gs[5] = z_c / H;
+        orc_local_gas lg;
+        orc_local_gas_at(P, r_c, z_c, &lg);
+        gs[0] = V; gs[1] = lg.rho_g; gs[2] = lg.T; gs[3] = lg.alpha; gs[4] = r_c; gs[5] = z_c / lg.H;
       } else {
         gs[0] = 0.0; gs[1] = 0.0; gs[2] = 0.0; gs[3] = 0.0; gs[4] = 0.0; gs[5] = 0.0;
       }
@@ -541,14 +619,15 @@ void orc_transport(const orc_params *P, int64_t N, double *r, double *z, const d
     if (!active[k]) continue;
     double rk = P->column ? P->r_col : r[k];
     double zk = z[k];
-    double Sg, T, cs, Om, H, rho;
-    orc_disk_local(P, rk, zk, &Sg, &T, &cs, &Om, &H, &rho);
+    orc_local_gas lg;
+    orc_local_gas_at(P, rk, zk, &lg);
+    const double cs = lg.cs, Om = lg.Omega, H = lg.H, rho = lg.rho_g;
     double v_th = sqrt(8.0 / PI) * cs;
     double lambda = P->mu * MH / (rho * SIGMA_H2);
     double nu = 0.5 * v_th * lambda;
     double a = cbrt(3.0 * m[k] / (4.0 * PI * P->rho_s));
     double St = orc_stopping_time(P, a, rho, v_th, lambda, nu) * Om;
-    double D = P->alpha * cs * H / (1.0 + St * St);
+    double D = lg.alpha * cs * H / (1.0 + St * St);
     double ur, uz;
     orc_uniforms(P, (uint32_t)k, 0u, step, 2u, &ur, &uz);
     double kick_r = 2.0 * ur - 1.0, kick_z = 2.0 * uz - 1.0;
@@ -564,11 +643,11 @@ void orc_transport(const orc_params *P, int64_t N, double *r, double *z, const d
     if (!P->column) {
       double v = 0.0, dr = 0.0;
       if (fl & ORC_TR_DRIFT) {
-        double eta_vK = 0.5 * cs * cs / (Om * rk) * (P->p + (P->q + 3.0) / 2.0);
+        double eta_vK = 0.5 * cs * cs / (Om * rk) * lg.slopeP;
         v += -2.0 * eta_vK * St / (1.0 + St * St);
       }
       if (fl & ORC_TR_MIX_R) {
-        v += D * (1.5 - P->q - P->p) / rk;
+        v += D * lg.corr / rk;
         dr = kick_r * sqrt(6.0 * D * dt);
       }
       double rn = rk + v * dt + dr;

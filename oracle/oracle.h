@@ -52,6 +52,20 @@ extern "C" {
 #define ORC_OUT_ERODED_SMALL 2 /* i is the small projectile: fragment draw up to m_i */
 #define ORC_OUT_FRAG 3
 
+/* gridded gas (post-processing of hydrodynamic output, the paper's
+ * Statement of Need): node values on n_r radii x n_z heights, stored as
+ * logarithms; orc_grid_fill builds it from plain node values */
+typedef struct {
+  int32_t n_r, n_z;
+  const double *lr;    /* [n_r] ln r of the radial nodes (increasing) */
+  const double *zn;    /* [n_z] heights of the vertical nodes (>= 0, increasing) */
+  const double *lrho;  /* [n_r*n_z] ln rho_g, radius-major */
+  const double *lT;    /* [n_r*n_z] ln T */
+  const double *lA;    /* [n_r*n_z] ln alpha */
+  const double *lS;    /* [n_r] ln Sigma_g: twice the trapezoid integral of rho_g over the
+                          nodes' heights plus z_0 rho_g(z_0) below the first node */
+} orc_gas_grid;
+
 typedef struct {
   double sigma_g0;      /* gas surface density at r_ref [g cm^-2] */
   double T0;            /* temperature at r_ref [K] */
@@ -78,7 +92,17 @@ typedef struct {
   int32_t frag_mode;    /* ORC_FRAG_*: how the relative velocity decides fragmentation */
   int32_t pad_;
   double frag_width;    /* ORC_FRAG_RAMP: relative width of the ramp below v_frag */
+  const orc_gas_grid *grid; /* gridded gas, or NULL for the power-law disk */
 } orc_params;
+
+/* gas at one point: density, temperature, turbulence, sound speed, Kepler
+ * frequency, scale height, the pressure slope s = -d ln P / d ln r (so that
+ * eta v_K = c_s^2 s / (2 Omega r)), and the radial-diffusion correction
+ * factor c, such that the random walk drifts by D c / r (the logarithmic
+ * r-derivative of Sigma_g alpha c_s H) */
+typedef struct {
+  double rho_g, T, alpha, cs, Omega, H, slopeP, corr;
+} orc_local_gas;
 
 /* per-cell gas record, six primaries: V, rho_g, T, alpha, r_c, zeta (= z_c/H) */
 #define ORC_GAS_FIELDS 6
@@ -107,6 +131,10 @@ typedef struct {
 } orc_cell_stats;
 
 /* --- building blocks (exported for pin tests) --- */
+void orc_grid_fill(int32_t n_r, int32_t n_z, const double *r_nodes, const double *z_nodes,
+                   const double *rho, const double *T, const double *alpha, double *lr, double *zn,
+                   double *lrho, double *lT, double *lA, double *lS);
+void orc_local_gas_at(const orc_params *P, double r, double z, orc_local_gas *o);
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double orc_u01(uint32_t lo, uint32_t hi);
 void orc_gas_derive(const orc_params *P, const double prim[ORC_GAS_FIELDS], orc_gas *g);
