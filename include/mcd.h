@@ -224,6 +224,24 @@ mcd_status mcd_tune(mcd_ctx *ctx, double dt, int64_t max_events_per_cell, mcd_tu
  * previous schedule is kept). */
 mcd_status mcd_set_schedule(mcd_ctx *ctx, int32_t small_max, int32_t grid_per_cu);
 
+/* Gridded gas in place of the power-law disk (post-processing a
+ * hydrodynamic state, the paper's Statement of Need).  Host arrays:
+ * r_nodes [n_gr] (> 0, increasing), z_nodes [n_gz] (heights above the
+ * midplane, >= 0, increasing), rho, T, alpha [n_gr][n_gz] (radius-major,
+ * positive), copied before the call returns.  Gas at (r, z): bilinear
+ * interpolation in (ln r, z) of ln rho_g, ln T and ln alpha, clamped to the
+ * boundary nodes outside; c_s from T, Omega from the star, H = c_s / Omega;
+ * eta v_K = c_s^2 s / (2 Omega r) with s = -d ln(rho_g T) / d ln r of the
+ * interpolant at (r, z); radial diffusion drifts by D c / r with
+ * c = d ln(Sigma_g alpha T) / d ln r + 3/2, Sigma_g(r_k) = 2 (z_0 rho(z_0) +
+ * trapezoids over the nodes).  Binning (cell gas), the rate matrix (eta v_K
+ * of explicit and adaptive cells) and transport use it from the next call
+ * on.  r_nodes == NULL restores the power-law disk.  Synchronises; MCD_EINVAL
+ * on bad nodes or values. */
+mcd_status mcd_set_gas_grid(mcd_ctx *ctx, const double *r_nodes, int32_t n_gr,
+                            const double *z_nodes, int32_t n_gz, const double *rho,
+                            const double *T, const double *alpha);
+
 /* sigma_d(m, r): dust surface density per particle-mass bin and radius of
  * the current particles (paper, Benchmark: the run's output is the dust
  * surface density as a function of particle mass and distance from the

@@ -27,7 +27,7 @@ GEOM_FIELDS = 5
 
 # every function declared in include/mcd.h
 EXPORTS = ("mcd_init", "mcd_bin", "mcd_rates", "mcd_step", "mcd_tune", "mcd_set_schedule",
-           "mcd_sigma_hist", "mcd_snapshot_bytes", "mcd_snapshot", "mcd_snapshot_wait",
+           "mcd_set_gas_grid", "mcd_sigma_hist", "mcd_snapshot_bytes", "mcd_snapshot", "mcd_snapshot_wait",
            "mcd_get_stats", "mcd_get_cells", "mcd_set_event_log", "mcd_philox", "mcd_last_error",
            "mcd_free")
 
@@ -88,6 +88,7 @@ def load() -> C.CDLL:
         "mcd_tune": (i32, [vp, C.c_double, i64, C.POINTER(TuneResult)]),
         "mcd_set_schedule": (i32, [vp, i32, i32]),
         "mcd_sigma_hist": (i32, [vp, vp, i32, vp, i32, vp, vp]),
+        "mcd_set_gas_grid": (i32, [vp, vp, i32, vp, i32, vp, vp, vp]),
         "mcd_snapshot_bytes": (i32, [vp, u32, C.POINTER(C.c_size_t)]),
         "mcd_snapshot": (i32, [vp, u32, vp, C.c_size_t, C.POINTER(i64)]),
         "mcd_snapshot_wait": (i32, [vp, i64]),

@@ -90,6 +90,22 @@ class Simulation:
         self._check(self.lib.mcd_set_schedule(self.ctx, int(small_max), int(grid_per_cu)),
                     "mcd_set_schedule")
 
+    def set_gas_grid(self, grid: dict | None) -> None:
+        """Gridded gas: dict of r_nodes [n_r], z_nodes [n_z], rho, T, alpha
+        [n_r, n_z] (host arrays); None restores the power-law disk."""
+        import numpy as np
+        if grid is None:
+            self._check(self.lib.mcd_set_gas_grid(self.ctx, None, 0, None, 0, None, None, None),
+                        "mcd_set_gas_grid")
+            return
+        rn = np.ascontiguousarray(grid["r_nodes"], dtype=np.float64)
+        zn = np.ascontiguousarray(grid["z_nodes"], dtype=np.float64)
+        f = [np.ascontiguousarray(grid[k], dtype=np.float64).reshape(len(rn), len(zn))
+             for k in ("rho", "T", "alpha")]
+        self._check(self.lib.mcd_set_gas_grid(self.ctx, rn.ctypes.data, len(rn), zn.ctypes.data,
+                                              len(zn), *[a.ctypes.data for a in f]),
+                    "mcd_set_gas_grid")
+
     def sigma_hist(self, r_edges, m_edges) -> tuple[torch.Tensor, torch.Tensor]:
         """sigma_d(m, r) [n_rb, n_mb] (g/cm^2 per mass bin) and particle counts
         of the current particles over the given bin edges."""

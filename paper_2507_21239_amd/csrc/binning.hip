@@ -558,11 +558,11 @@ __global__ __launch_bounds__(256) void k_cells(Model P, int n_r, int n_z,
   gm[4] = V;
   double *gs = gas + (size_t)c * 6;
   if (s1 > s0) {
-    const DiskPoint d = disk_at(P, r_c, z_c);
+    const LocalGas d = local_gas_at(P, r_c, z_c);
     gs[0] = V;
     gs[1] = d.rho_g;
     gs[2] = d.T;
-    gs[3] = P.alpha;
+    gs[3] = d.alpha;
     gs[4] = r_c;
     gs[5] = z_c / d.H;
   } else {

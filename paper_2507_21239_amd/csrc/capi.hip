@@ -52,6 +52,8 @@ struct mcd_ctx {
   hipEvent_t ev_staged[2] = {nullptr, nullptr}, ev_landed[2] = {nullptr, nullptr};
   bool slot_used[2] = {false, false};
   int64_t snap_count = 0;
+  double *d_grid = nullptr;     // gridded gas: lr, zn, lrho, lT, lA, lS back to back
+  std::vector<double> h_grid;
   std::vector<double> h_edges;  // histogram bin edges (host copy, read by the async upload)
   double *d_edges = nullptr;
   size_t edges_cap = 0;
@@ -617,6 +619,73 @@ mcd_status mcd_tune(mcd_ctx *c, double dt, int64_t max_events, mcd_tune_result *
   return MCD_OK;
 }
 
+mcd_status mcd_set_gas_grid(mcd_ctx *c, const double *r_nodes, int32_t n_gr, const double *z_nodes,
+                            int32_t n_gz, const double *rho, const double *T, const double *alpha) {
+  if (!c) return MCD_EINVAL;
+  if (!r_nodes) {  // back to the power-law disk
+    MCD_HIP(c, hipStreamSynchronize(c->stream));
+    dfree(c->d_grid);
+    c->d_grid = nullptr;
+    c->model.grid = GasGridView{};
+    drop_graph(c);
+    return MCD_OK;
+  }
+  if (n_gr < 2 || n_gz < 2 || (int64_t)n_gr * n_gz > ((int64_t)1 << 24) || !z_nodes || !rho || !T ||
+      !alpha)
+    return fail(c, MCD_EINVAL, "the gas grid needs n_gr, n_gz >= 2 and all node arrays");
+  for (int32_t k = 0; k < n_gr; ++k)
+    if (!(std::isfinite(r_nodes[k]) && r_nodes[k] > 0.0) || (k && !(r_nodes[k] > r_nodes[k - 1])))
+      return fail(c, MCD_EINVAL, "r_nodes must be positive, finite and strictly increasing");
+  for (int32_t l = 0; l < n_gz; ++l)
+    if (!(std::isfinite(z_nodes[l]) && z_nodes[l] >= 0.0) || (l && !(z_nodes[l] > z_nodes[l - 1])))
+      return fail(c, MCD_EINVAL, "z_nodes must be >= 0, finite and strictly increasing");
+  const size_t nn = (size_t)n_gr * n_gz;
+  for (size_t i = 0; i < nn; ++i)
+    if (!(std::isfinite(rho[i]) && rho[i] > 0.0 && std::isfinite(T[i]) && T[i] > 0.0 &&
+          std::isfinite(alpha[i]) && alpha[i] > 0.0))
+      return fail(c, MCD_EINVAL, "rho, T and alpha must be positive and finite at every node");
+  // logarithms at the nodes and the surface density of every radial node:
+  // twice (z_0 rho(z_0) + trapezoids over the nodes' heights)
+  const size_t total = (size_t)n_gr + n_gz + 3 * nn + n_gr;
+  std::vector<double> h(total);
+  double *lr = h.data(), *zn = lr + n_gr, *lrho = zn + n_gz, *lT = lrho + nn, *lA = lT + nn,
+         *lS = lA + nn;
+  for (int32_t k = 0; k < n_gr; ++k) lr[k] = std::log(r_nodes[k]);
+  for (int32_t l = 0; l < n_gz; ++l) zn[l] = z_nodes[l];
+  for (int32_t k = 0; k < n_gr; ++k) {
+    double col = z_nodes[0] * rho[(size_t)k * n_gz];
+    for (int32_t l = 0; l < n_gz; ++l) {
+      const size_t i = (size_t)k * n_gz + l;
+      lrho[i] = std::log(rho[i]);
+      lT[i] = std::log(T[i]);
+      lA[i] = std::log(alpha[i]);
+      if (l + 1 < n_gz) col += (z_nodes[l + 1] - z_nodes[l]) * (rho[i] + rho[i + 1]) / 2.0;
+    }
+    lS[k] = std::log(2.0 * col);
+  }
+  MCD_HIP(c, hipStreamSynchronize(c->stream));  // no queued kernel reads the old grid
+  dfree(c->d_grid);
+  c->d_grid = nullptr;
+  c->model.grid = GasGridView{};
+  if (dalloc(&c->d_grid, total) != hipSuccess)
+    return fail(c, MCD_ENOMEM, "device allocation of the gas grid failed");
+  c->h_grid.swap(h);
+  MCD_HIP(c, hipMemcpyAsync(c->d_grid, c->h_grid.data(), total * sizeof(double),
+                            hipMemcpyHostToDevice, c->stream));
+  GasGridView g;
+  g.lr = c->d_grid;
+  g.zn = g.lr + n_gr;
+  g.lrho = g.zn + n_gz;
+  g.lT = g.lrho + nn;
+  g.lA = g.lT + nn;
+  g.lS = g.lA + nn;
+  g.nr = n_gr;
+  g.nz = n_gz;
+  c->model.grid = g;
+  drop_graph(c);
+  return MCD_OK;
+}
+
 mcd_status mcd_sigma_hist(mcd_ctx *c, const double *r_edges, int32_t n_rb, const double *m_edges,
                           int32_t n_mb, double *sigma, uint32_t *count) {
   if (!c) return MCD_EINVAL;
@@ -813,6 +882,7 @@ void mcd_free(mcd_ctx *c) {
   BinBuffers &b = c->bb;
   free_binning(b);
   dfree(c->d_edges);
+  dfree(c->d_grid);
   dfree(c->d_mbak);
   dfree(c->d_cbak);
   dfree(c->d_sbak);

@@ -42,15 +42,123 @@ enum { K_PHYSICAL = 0, K_CONSTANT = 1, K_LINEAR = 2 };
 enum { OUT_STICK = 0, OUT_ERODE = 1, OUT_ERODED_SMALL = 2, OUT_FRAG = 3 };
 
 // model constants copied to the device by value
+// gridded gas on the device: node values on nr radii x nz heights, as
+// logarithms (nr == 0: the power-law disk)
+struct GasGridView {
+  const double *lr;    // [nr] ln r of the radial nodes
+  const double *zn;    // [nz] heights of the vertical nodes
+  const double *lrho;  // [nr][nz] ln rho_g
+  const double *lT;    // [nr][nz] ln T
+  const double *lA;    // [nr][nz] ln alpha
+  const double *lS;    // [nr] ln Sigma_g
+  int32_t nr, nz;
+};
+
 struct Model {
   double sigma_g0, T0, p, q, alpha, v_frag, erosion_ratio, rho_s, mu, m_star, r_ref;
   double dm_max, erosion_chi, r_in, r_col, k0, m0, frag_width;
   uint32_t flags;
   int32_t kernel, column, n_comp, frag_mode;
   uint32_t key0, key1;
+  GasGridView grid;
 };
 
 enum : int32_t { FRAG_SHARP = 0, FRAG_RAMP = 1, FRAG_MAXWELL = 2 };
+
+struct DiskPoint {
+  double Sigma_g, T, cs, Omega, H, rho_g;
+};
+
+__host__ __device__ inline DiskPoint disk_at(const Model &P, double r, double z) {
+  DiskPoint d;
+  const double x = r / P.r_ref;
+  d.Sigma_g = P.sigma_g0 * pow(x, -P.p);
+  d.T = P.T0 * pow(x, -P.q);
+  d.cs = sqrt(kBoltz * d.T / (P.mu * kMassH));
+  d.Omega = sqrt(kGrav * P.m_star / (r * r * r));
+  d.H = d.cs / d.Omega;
+  d.rho_g = d.Sigma_g / (sqrt(2.0 * kPi) * d.H) * exp(-(z * z) / (2.0 * d.H * d.H));
+  return d;
+}
+
+// gas at one point: density, temperature, turbulence, sound speed, Kepler
+// frequency, scale height, pressure slope s = -d ln P / d ln r (eta v_K =
+// c_s^2 s / (2 Omega r)) and the radial-diffusion correction factor c (the
+// random walk drifts by D c / r: the logarithmic r-derivative of
+// Sigma_g alpha c_s H)
+struct LocalGas {
+  double rho_g, T, alpha, cs, Omega, H, slopeP, corr;
+};
+
+// cell of a node array containing x, clamped to the first / last cell, and
+// the fractional position in it (0 or 1 outside the nodes)
+__host__ __device__ inline void grid_locate(const double *nodes, int n, double x, int &k,
+                                            double &w) {
+  if (!(x > nodes[0])) {
+    k = 0;
+    w = 0.0;
+    return;
+  }
+  if (!(x < nodes[n - 1])) {
+    k = n - 2;
+    w = 1.0;
+    return;
+  }
+  int lo = 0, hi = n - 1;  // nodes[lo] <= x < nodes[hi]
+  while (hi - lo > 1) {
+    const int mid = lo + (hi - lo) / 2;
+    if (x < nodes[mid])
+      hi = mid;
+    else
+      lo = mid;
+  }
+  k = lo;
+  w = (x - nodes[lo]) / (nodes[lo + 1] - nodes[lo]);
+}
+
+// power-law disk, or the gridded gas: bilinear in (ln r, z) of ln rho_g,
+// ln T and ln alpha, with the r-slopes of those interpolants at this height;
+// the surface density's slope from its radial nodes
+__host__ __device__ inline LocalGas local_gas_at(const Model &P, double r, double z) {
+  LocalGas o;
+  const GasGridView &G = P.grid;
+  if (G.nr == 0) {
+    const DiskPoint d = disk_at(P, r, z);
+    o.rho_g = d.rho_g;
+    o.T = d.T;
+    o.cs = d.cs;
+    o.Omega = d.Omega;
+    o.H = d.H;
+    o.alpha = P.alpha;
+    o.slopeP = P.p + (P.q + 3.0) / 2.0;
+    o.corr = 1.5 - P.q - P.p;
+    return o;
+  }
+  int k, l;
+  double wx, wz;
+  grid_locate(G.lr, G.nr, log(r), k, wx);
+  grid_locate(G.zn, G.nz, z, l, wz);
+  const int64_t i00 = (int64_t)k * G.nz + l, i10 = i00 + G.nz, i01 = i00 + 1, i11 = i10 + 1;
+  const double dx = G.lr[k + 1] - G.lr[k];
+  const double *f[3] = {G.lrho, G.lT, G.lA};
+  double val[3], slope[3];
+  for (int q = 0; q < 3; ++q) {
+    const double *a = f[q];
+    val[q] = (1.0 - wx) * (1.0 - wz) * a[i00] + wx * (1.0 - wz) * a[i10] +
+             (1.0 - wx) * wz * a[i01] + wx * wz * a[i11];
+    slope[q] = ((1.0 - wz) * (a[i10] - a[i00]) + wz * (a[i11] - a[i01])) / dx;
+  }
+  o.rho_g = exp(val[0]);
+  o.T = exp(val[1]);
+  o.alpha = exp(val[2]);
+  o.cs = sqrt(kBoltz * o.T / (P.mu * kMassH));
+  o.Omega = sqrt(kGrav * P.m_star / (r * r * r));
+  o.H = o.cs / o.Omega;
+  o.slopeP = -(slope[0] + slope[1]);  // pressure rho_g c_s^2 ~ rho_g T
+  const double dlnS = (G.lS[k + 1] - G.lS[k]) / dx;
+  o.corr = dlnS + slope[2] + slope[1] + 1.5;
+  return o;
+}
 
 // gas state of a cell, from its six primaries (V, rho_g, T, alpha, r_c,
 // zeta = z_c / H)
@@ -71,7 +179,8 @@ __host__ __device__ inline void gas_from_primaries(const Model &P, const double 
   g.H = g.cs / g.Omega;
   g.z_c = g.zeta * g.H;
   // midplane pressure-gradient velocity: P ~ r^-(p + (q+3)/2)
-  g.eta_vK = 0.5 * (g.cs * g.cs) / (g.Omega * g.r_c) * (P.p + (P.q + 3.0) / 2.0);
+  g.eta_vK = 0.5 * (g.cs * g.cs) / (g.Omega * g.r_c) *
+             (P.grid.nr ? local_gas_at(P, g.r_c, g.z_c).slopeP : (P.p + (P.q + 3.0) / 2.0));
   g.v_th = sqrt(8.0 / kPi) * g.cs;
   g.lambda = P.mu * kMassH / (g.rho_g * kSigmaH2);
   g.nu = 0.5 * g.v_th * g.lambda;
@@ -81,22 +190,6 @@ __host__ __device__ inline void gas_from_primaries(const Model &P, const double 
 }
 
 // power-law disk at (r, z): Sigma_g, T, c_s, Omega, H, rho_g
-struct DiskPoint {
-  double Sigma_g, T, cs, Omega, H, rho_g;
-};
-
-__host__ __device__ inline DiskPoint disk_at(const Model &P, double r, double z) {
-  DiskPoint d;
-  const double x = r / P.r_ref;
-  d.Sigma_g = P.sigma_g0 * pow(x, -P.p);
-  d.T = P.T0 * pow(x, -P.q);
-  d.cs = sqrt(kBoltz * d.T / (P.mu * kMassH));
-  d.Omega = sqrt(kGrav * P.m_star / (r * r * r));
-  d.H = d.cs / d.Omega;
-  d.rho_g = d.Sigma_g / (sqrt(2.0 * kPi) * d.H) * exp(-(z * z) / (2.0 * d.H * d.H));
-  return d;
-}
-
 __host__ __device__ inline double stopping_time(double rho_s, double a, double rho_g, double v_th,
                                                 double lambda, double nu) {
   if (a < 2.25 * lambda) return rho_s * a / (rho_g * v_th);  // Epstein

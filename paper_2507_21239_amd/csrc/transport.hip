@@ -23,13 +23,13 @@ __global__ __launch_bounds__(256) void transport_kernel(Model P, double *__restr
   const uint32_t step = st->step;
   const double rk = P.column ? P.r_col : r[k];
   const double zk = z[k];
-  const DiskPoint d = disk_at(P, rk, zk);
+  const LocalGas d = local_gas_at(P, rk, zk);
   const double v_th = sqrt(8.0 / kPi) * d.cs;
   const double lambda = P.mu * kMassH / (d.rho_g * kSigmaH2);
   const double nu = 0.5 * v_th * lambda;
   const double a = cbrt(3.0 * m[k] / (4.0 * kPi * P.rho_s));
   const double St = stopping_time(P.rho_s, a, d.rho_g, v_th, lambda, nu) * d.Omega;
-  const double D = P.alpha * d.cs * d.H / (1.0 + St * St);
+  const double D = d.alpha * d.cs * d.H / (1.0 + St * St);
   const U4 w = philox4x32_10(U4{(uint32_t)k, 0u, step, 2u}, P.key0, P.key1);
   const double kick_r = 2.0 * u01(w.x, w.y) - 1.0;
   const double kick_z = 2.0 * u01(w.z, w.w) - 1.0;
@@ -45,11 +45,11 @@ __global__ __launch_bounds__(256) void transport_kernel(Model P, double *__restr
   if (!P.column) {
     double v = 0.0, dr = 0.0;
     if (P.flags & TR_DRIFT) {
-      const double eta_vK = 0.5 * d.cs * d.cs / (d.Omega * rk) * (P.p + (P.q + 3.0) / 2.0);
+      const double eta_vK = 0.5 * d.cs * d.cs / (d.Omega * rk) * d.slopeP;
       v += -2.0 * eta_vK * St / (1.0 + St * St);
     }
     if (P.flags & TR_MIX_R) {
-      v += D * (1.5 - P.q - P.p) / rk;
+      v += D * d.corr / rk;
       dr = kick_r * sqrt(6.0 * D * dt);
     }
     const double rn = rk + v * dt + dr;

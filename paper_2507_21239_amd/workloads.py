@@ -143,6 +143,33 @@ def c5_large_disk(seed: int = 0, N: int = 2_000_000, n_r: int = 1000, n_z: int =
     return out
 
 
+def gridded_gas(params: dict, n_r: int = 48, n_z: int = 24, r_lo: float = 0.5 * AU,
+                r_hi: float = 200.0 * AU, seed: int = 0) -> dict:
+    """A synthetic gas state on a grid (standing in for hydrodynamic output):
+    the power-law disk's midplane density and temperature with a Gaussian
+    pressure bump near 10 AU and a gap near 30 AU, scale heights from the
+    local temperature, a vertical density floor, turbulence rising outwards
+    and a small seeded ripple.  Node values only; no physics of the method."""
+    rng = np.random.default_rng(seed)
+    rn = np.geomspace(r_lo, r_hi, n_r)
+    x = rn / params["r_ref"]
+    T = params["T0"] * x ** -params["q"]
+    cs2 = 1.380649e-16 * T / (params["mu"] * 1.6735575e-24)
+    Om = np.sqrt(6.67430e-8 * params["m_star"] / rn ** 3)
+    H = np.sqrt(cs2) / Om
+    sig = params["sigma_g0"] * x ** -params["p"]
+    sig *= 1.0 + 1.5 * np.exp(-0.5 * ((np.log(rn / (10 * AU))) / 0.15) ** 2)
+    sig *= 1.0 - 0.9 * np.exp(-0.5 * ((np.log(rn / (30 * AU))) / 0.1) ** 2)
+    zn = np.linspace(0.0, 5.0 * H.max(), n_z)
+    rho_mid = sig / (np.sqrt(2 * np.pi) * H)
+    rho = rho_mid[:, None] * np.exp(-0.5 * (zn[None, :] / H[:, None]) ** 2)
+    rho = np.maximum(rho, 1e-12 * rho_mid[:, None])
+    rho *= 1.0 + 0.02 * rng.standard_normal(rho.shape)
+    Tg = np.repeat(T[:, None], n_z, axis=1) * (1.0 + 0.3 * (zn[None, :] / zn[-1]) ** 2)
+    alpha = np.repeat((params["alpha"] * (1.0 + 0.5 * np.log10(x / x[0])))[:, None], n_z, axis=1)
+    return dict(r_nodes=rn, z_nodes=zn, rho=rho, T=Tg, alpha=alpha)
+
+
 def c4_batched(seed: int = 0, n_cells: int = 4096, n_lo: int = 64, n_hi: int = 1024,
                events: int = 1000, philox_seed: int = 0, V: float = 1e36,
                counts=None) -> dict:
