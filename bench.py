@@ -263,6 +263,54 @@ def error_report(work, n_sample=8):
     ks = sst.ks_2samp(np.concatenate(om_all), np.concatenate(gm_all))
     out["mixed_vs_oracle_logm_ks_D"] = float(ks.statistic)
     out["mixed_vs_oracle_logm_ks_p"] = float(ks.pvalue)
+    out["ensemble"] = ensemble_report(work, pick)
+    return out
+
+
+def ensemble_report(work, pick, seeds=8, steps=2):
+    """Mixed GPU form vs the FP64 oracle over Philox seeds: the sampled cells,
+    `steps` steps of 1000 events each; per seed the moment ratios M1/M0,
+    M2/M1, M3/M2 of the swarms (M_k = sum N_i m_i^k, N_i = M_i/m_i), then
+    their ensemble means, relative differences and standard errors, and a
+    KS test on the pooled log10 m."""
+    import numpy as np
+    from scipy import stats as sst
+
+    import oracle as O
+    from paper_2507_21239_amd import api
+    from paper_2507_21239_amd import workloads as W
+
+    def ratios(m, M):
+        N = M / m
+        return [M.sum() / N.sum(), (M * m).sum() / M.sum(), (M * m * m).sum() / (M * m).sum()]
+
+    sub = W.subset_cells(work, np.array(pick))
+    ro, rg, lo, lg = [], [], [], []
+    for seed in range(seeds):
+        p = dict(sub["params"], seed=seed)
+        ref = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in sub["particles"].items()}
+        for s in range(steps):
+            O.collide_all(p, sub["cells"], s, ref, 0.0, EVENTS_PER_CELL, threads=os.cpu_count() or 1)
+        dev = api.to_device(sub["particles"])
+        sim = api.Simulation(p, dev, precision="mixed", schedule="batched")
+        sim.bin(api.cells_to_device(sub["cells"]))
+        sim.step(0.0, EVENTS_PER_CELL, steps)
+        g = dev["m"].cpu().numpy()
+        sim.close()
+        ro.append(ratios(ref["m"], ref["M"]))
+        rg.append(ratios(g, sub["particles"]["M"]))
+        lo.append(np.log10(ref["m"]))
+        lg.append(np.log10(g))
+    ro, rg = np.array(ro), np.array(rg)
+    se = lambda x: float(x.std(ddof=1) / np.sqrt(len(x)))
+    out = {"seeds": seeds, "steps": steps, "cells": len(pick)}
+    for k, name in enumerate(("M1/M0", "M2/M1", "M3/M2")):
+        mo, mg = float(ro[:, k].mean()), float(rg[:, k].mean())
+        out[name] = {"oracle": mo, "mixed": mg, "rel_diff": (mg - mo) / mo,
+                     "rel_se": float(np.hypot(se(ro[:, k]), se(rg[:, k])) / mo)}
+    ks = sst.ks_2samp(np.concatenate(lo), np.concatenate(lg))
+    out["logm_ks_D"] = float(ks.statistic)
+    out["logm_ks_p"] = float(ks.pvalue)
     return out
 
 
