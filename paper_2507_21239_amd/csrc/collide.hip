@@ -373,7 +373,14 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     return;
   }
   Gas g;
-  gas_from_primaries(A.P, A.gas + (size_t)cell * 6, g);
+  {
+    // grid sizes opaque per cell: the node lookups' bounds are formed here
+    // instead of being held through every cell of a persistent launch
+    Model Pl = A.P;
+    Pl.grid.nr = opaque_s(Pl.grid.nr);
+    Pl.grid.nz = opaque_s(Pl.grid.nz);
+    gas_from_primaries(Pl, A.gas + (size_t)cell * 6, g);
+  }
   if (!(g.V > 0.0)) {
     if (tl == 0) atomicOr(&A.state->flags, FLAG_BAD_VOLUME);
     return;
@@ -466,7 +473,11 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
   // event e0 + l from Philox(e0 + l, cell, step, 0) and (.., 1)
   double nlu1 = 0.0, uu2 = 0.0, uu3 = 0.0, uu4 = 0.0;
   int64_t e0 = -64;
+  const int K_cell = K;
   for (;;) {
+    // K per event: tests of q < K are made where they are needed instead of
+    // being kept as lane masks across the loop
+    const int K = opaque_s(K_cell);
     if (!(Rtot > 0.0) || !isfinite(Rtot)) {
       if (!isfinite(Rtot) && tl == 0) atomicOr(&A.state->flags, FLAG_BAD_RATE);
       break;
@@ -475,8 +486,10 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     if (e - e0 >= 64) {
       e0 = e;
       const uint32_t ec = (uint32_t)(e + lane);
-      const U4 w0 = philox4x32_10(U4{ec, c32, step, 0u}, A.P.key0, A.P.key1);
-      const U4 w1 = philox4x32_10(U4{ec, c32, step, 1u}, A.P.key0, A.P.key1);
+      // the key schedule is formed here, once per 64 events, not held
+      const uint32_t k0 = opaque_s(A.P.key0), k1 = opaque_s(A.P.key1);
+      const U4 w0 = philox4x32_10(U4{ec, c32, step, 0u}, k0, k1);
+      const U4 w1 = philox4x32_10(U4{ec, c32, step, 1u}, k0, k1);
       if (timed) nlu1 = -log(u01(w0.x, w0.y));
       uu2 = u01(w0.z, w0.w);
       uu3 = u01(w1.x, w1.y);

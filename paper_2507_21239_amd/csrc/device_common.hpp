@@ -74,6 +74,17 @@ __device__ inline double readlane_d(double x, int lane) {
 
 __device__ inline int readlane_i(int x, int lane) { return __builtin_amdgcn_readlane(x, lane); }
 
+// a wave-uniform 32-bit value returned unchanged but hidden from the
+// optimizer: what is derived from it is recomputed where it is used rather
+// than hoisted out of an enclosing loop and held (or spilled) for the loop's
+// whole duration
+template <typename T>
+__device__ inline T opaque_s(T x) {
+  static_assert(sizeof(T) == 4, "32-bit values");
+  asm volatile("" : "+s"(x));
+  return x;
+}
+
 // inclusive prefix sum over the 64 lanes: shifts of 1, 2, 4, 8 inside rows of
 // 16 lanes, then row broadcasts of lanes 15 and 31 (gfx9 DPP)
 __device__ inline double wave_incl_scan(double x) {
