@@ -120,7 +120,18 @@ struct Team {
     else
       wave_lds_sync();
   }
-  // team-inclusive prefix of x over team lanes; total on every lane
+  // the four wave totals of exchange slot k (two 16-byte LDS reads)
+  __device__ void totals4(int k, double t[4]) const {
+    const double2 a = ((const double2 *)S->tot[phase])[2 * k];
+    const double2 b = ((const double2 *)S->tot[phase])[2 * k + 1];
+    t[0] = a.x;
+    t[1] = a.y;
+    t[2] = b.x;
+    t[3] = b.y;
+  }
+  // team-inclusive prefix of x over team lanes; total on every lane.  Teams
+  // have one wave or four; the offset and total add the wave totals in wave
+  // order
   __device__ double scan(double x, double &total) {
     const double inc = wave_incl_scan(x);
     const double wt = readlane_d(inc, 63);
@@ -131,11 +142,13 @@ struct Team {
     phase ^= 1;
     if (lane == 63) S->tot[phase][wave] = wt;
     block_lds_sync();
+    double t[4];
+    totals4(0, t);
     double off = 0.0, tot = 0.0;
-    for (int w = 0; w < nw; ++w) {
-      const double v = S->tot[phase][w];
-      if (w < wave) off += v;
-      tot += v;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      if (w < wave) off += t[w];
+      tot += t[w];
     }
     total = tot;
     return off + inc;
@@ -156,12 +169,15 @@ struct Team {
       S->tot[phase][4 + wave] = wb;
     }
     block_lds_sync();
+    double ta4[4], tb4[4];
+    totals4(0, ta4);
+    totals4(1, tb4);
     double off = 0.0, ta = 0.0, tb = 0.0;
-    for (int w = 0; w < nw; ++w) {
-      const double v = S->tot[phase][w];
-      if (w < wave) off += v;
-      ta += v;
-      tb += S->tot[phase][4 + w];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      if (w < wave) off += ta4[w];
+      ta += ta4[w];
+      tb += tb4[w];
     }
     tot_a = ta;
     tot_b = tb;
@@ -243,15 +259,18 @@ __device__ inline bool wave_pick(int wave, double incl, double part, const VT *v
 // delta from team lane 64 fix_wave on), so every wave finds the same owner
 // without another exchange.  -1 if no wave's prefix exceeds the target.
 __device__ inline int owner_wave(const Team &tm, double target, int fix_wave, double delta) {
+  double t[4];
+  tm.totals4(0, t);
   double off = 0.0;
-  for (int w = 0; w < tm.nw; ++w) {
-    const double wt = tm.S->tot[tm.phase][w];
-    double cum = off + wt;
+  int ow = -1;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    double cum = off + t[w];
     if (w >= fix_wave) cum += delta;
-    if (cum > target) return w;
-    off += wt;
+    if (ow < 0 && cum > target) ow = w;
+    off += t[w];
   }
-  return -1;
+  return ow;
 }
 
 // Every wave searches and publishes its candidate; the team takes the first
@@ -431,27 +450,44 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
   tm.sync();
 
   // ---- row sums r_i = sum_k r_ik, k in canonical order ------------------
+  // Partners k = 0..n-1 are read once per group of G own slots and paired
+  // with each of them (independent evaluations); each row still adds its
+  // terms in canonical order.
   double r[KMAX];
-  const int lanes_used = (n + K - 1) / K;
+  {
+    constexpr int G = sizeof(RT) == 4 ? 4 : 2;
+    static_assert(KMAX % G == 0, "slot groups");
 #pragma unroll
-  for (int q = 0; q < KMAX; ++q) r[q] = 0.0;
-#pragma unroll 1
-  for (int q = 0; q < K; ++q) {
-    if (tl * K + q >= n) break;
-    const Rec<RT> mine = R.load(q * TL + tl);
-    RT acc = (RT)0;
-    for (int t2 = 0; t2 < lanes_used; ++t2) {
-      for (int q2 = 0; q2 < K; ++q2) {
-        if (t2 * K + q2 >= n) break;
-        const Rec<RT> rk = R.load(q2 * TL + t2);
-        RT dv, rxy, ryx;
-        PairEval<RT, FAST>::run(pc, mine, rk, dv, rxy, ryx);
-        acc += rxy;
+    for (int q0 = 0; q0 < KMAX; q0 += G) {
+      Rec<RT> mine[G];
+      RT acc[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        acc[g] = (RT)0;
+        if (q0 + g < K) mine[g] = R.load((q0 + g) * TL + tl);
       }
-    }
+      if (q0 < K) {
+        int t2 = 0, q2 = 0;
+        for (int k = 0; k < n; ++k) {
+          const Rec<RT> rk = R.load(q2 * TL + t2);
 #pragma unroll
-    for (int qq = 0; qq < KMAX; ++qq)
-      if (qq == q) r[qq] = (double)acc;
+          for (int g = 0; g < G; ++g) {
+            if (q0 + g < K) {
+              RT dv, rxy, ryx;
+              PairEval<RT, FAST>::run(pc, mine[g], rk, dv, rxy, ryx);
+              acc[g] += rxy;
+            }
+          }
+          if (++q2 == K) {
+            q2 = 0;
+            ++t2;
+          }
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        r[q0 + g] = (q0 + g < K && tl * K + q0 + g < n) ? (double)acc[g] : 0.0;
+    }
   }
 
   // ---- events ------------------------------------------------------------
@@ -629,7 +665,7 @@ template <typename RT, int KMAX, bool FAST, bool PROB>
 __global__ __launch_bounds__(256, sizeof(RT) == 4 ? 3 : 2) void collide_batched(CollideArgs A) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_item;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const uint32_t step = A.state->step;
   const size_t small_bytes = region_bytes<RT>(A.small_cap, 1);
   int nw = A.n_big > 0 ? 4 : 1;
@@ -662,8 +698,9 @@ __global__ __launch_bounds__(256, sizeof(RT) == 4 ? 3 : 2) void collide_batched(
 template <typename RT, int KMAX, bool FAST, bool PROB>
 __global__ __launch_bounds__(256) void collide_plain(CollideArgs A) {
   extern __shared__ __align__(16) char smem[];
-  process_cell<RT, KMAX, FAST, PROB>(A, blockIdx.x, smem, A.big_cap, 4, threadIdx.x >> 6, threadIdx.x & 63,
-                         A.state->step);
+  process_cell<RT, KMAX, FAST, PROB>(A, blockIdx.x, smem, A.big_cap, 4,
+                                     __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
+                                     threadIdx.x & 63, A.state->step);
 }
 
 __global__ void reset_queues(DevState *st) {

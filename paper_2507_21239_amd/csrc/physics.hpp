@@ -401,6 +401,10 @@ __device__ inline void pair_rates_all(const PairConst<float> &c, const Rec<float
   constexpr float ya = (float)kYa;
   constexpr float c1 = (float)(1.0 / (1.0 + kYa));
   constexpr float b0 = (float)(2.0 * kYa - 1.0);
+  // h and q1 in registers before the arithmetic: otherwise their loads are
+  // deferred into the turbulence-regime branches, a second wait on LDS per
+  // pair
+  asm volatile("" ::"v"(x.h), "v"(x.q1), "v"(y.h), "v"(y.q1));
   float dv2 = c.cBM * (x.im + y.im);
   const bool xb = x.St > y.St;
   const float St1 = xb ? x.St : y.St;
