@@ -402,8 +402,7 @@ __device__ inline void pair_rates_all(const PairConst<float> &c, const Rec<float
   constexpr float c1 = (float)(1.0 / (1.0 + kYa));
   constexpr float b0 = (float)(2.0 * kYa - 1.0);
   // h and q1 in registers before the arithmetic: otherwise their loads are
-  // deferred into the turbulence-regime branches, a second wait on LDS per
-  // pair
+  // deferred into the regime choice, a second wait on LDS per pair
   asm volatile("" ::"v"(x.h), "v"(x.q1), "v"(y.h), "v"(y.q1));
   float dv2 = c.cBM * (x.im + y.im);
   const bool xb = x.St > y.St;
@@ -416,7 +415,12 @@ __device__ inline void pair_rates_all(const PairConst<float> &c, const Rec<float
   const float tiny = (1.0f - eps) * (ye * rd) * hd;
   const float inter = St1 * (b0 - eps + 2.0f * rd * fmaf(ye, c1, eps * eps * eps));
   const float heavy = x.q1 + y.q1;
-  const float turb = St1 < c.St_eta ? tiny : (St1 < 1.0f ? inter : heavy);
+  // the regime is chosen by selects, not branches: the two candidate values
+  // pass through an empty asm so that the optimizer cannot sink their
+  // arithmetic into per-regime blocks (which serialise a wave's pairs)
+  float tn = tiny, it = inter;
+  asm("" : "+v"(tn), "+v"(it));
+  const float turb = St1 < c.St_eta ? tn : (St1 < 1.0f ? it : heavy);
   dv2 = fmaf(c.Vg2, turb, dv2);
   float d = x.vr - y.vr;
   dv2 = fmaf(d, d, dv2);
