@@ -337,19 +337,20 @@ __device__ inline int event_outcome(const CollideArgs &A, const TeamScratch *S, 
                                     double mj, double Mi, RT dvj, double u4, int gi, int gj,
                                     int lane, bool writer, uint32_t e, uint32_t cell,
                                     uint32_t step, double &mnew, Rec<RT> &rin) {
+  const OutcomeConst &P = S->oc;
   bool fast;
   if constexpr (PROB) {
     const U4 w = philox4x32_10(U4{e, cell, step, 3u}, A.P.key0, A.P.key1);
-    fast = u01(w.x, w.y) < frag_probability(A.P, (double)dvj);
+    fast = u01(w.x, w.y) < frag_probability(P, (double)dvj);
   } else {
-    fast = !(dvj < (RT)A.P.v_frag);
+    fast = !(dvj < (RT)P.v_frag);
   }
-  const int oc = outcome(A.P, fast, mi, mj, u4, mnew);
+  const int oc = outcome(P, fast, mi, mj, u4, mnew);
   if (writer) {
     if ((!(mnew > 0.0) || !isfinite(mnew)) && lane == 0) atomicOr(&A.state->flags, FLAG_BAD_MASS);
-    if (A.comp != nullptr && A.P.n_comp > 0 && (oc == OUT_STICK || oc == OUT_FRAG) &&
-        lane < A.P.n_comp) {
-      const double wi = mi, wj = group_factor(A.P.dm_max, mi, mj) * mj;
+    if (A.comp != nullptr && P.n_comp > 0 && (oc == OUT_STICK || oc == OUT_FRAG) &&
+        lane < P.n_comp) {
+      const double wi = mi, wj = group_factor(P.dm_max, mi, mj) * mj;
       float *cs = A.comp + (size_t)lane * A.N;
       const double cI = (double)cs[gi], cJ = (double)cs[gj];
       cs[gi] = (float)((wi * cI + wj * cJ) / (wi + wj));
@@ -437,6 +438,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
   if (tl == 0) {
     tm.S->gas = g;
     tm.S->cf = make_cellf(A.P, g, scale);
+    tm.S->oc = make_outcome_const(A.P);
   }
   uint32_t valid = 0;  // bit q: slot q holds a particle
 #pragma unroll

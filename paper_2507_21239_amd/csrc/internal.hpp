@@ -55,12 +55,14 @@ struct Cand {
 };
 
 // team scratch after a region's particle records: wave totals, selection
-// candidates (double-buffered) and the cell's gas state
+// candidates (double-buffered), the cell's gas state and the outcome
+// parameters
 struct TeamScratch {
   double tot[2][8];
   Cand cand[2][4];
   Gas gas;
   CellF cf;
+  OutcomeConst oc;
 };
 
 // LDS bytes of one particle record in rate precision RT

@@ -65,6 +65,29 @@ struct Model {
 
 enum : int32_t { FRAG_SHARP = 0, FRAG_RAMP = 1, FRAG_MAXWELL = 2 };
 
+// the model parameters a collision outcome reads, gathered per cell into the
+// team's LDS scratch: read there once per event instead of being held (and
+// spilled) in scalar registers for the whole persistent launch
+struct OutcomeConst {
+  double v_frag, erosion_ratio, erosion_chi, m0, dm_max, frag_width;
+  int32_t kernel, frag_mode, n_comp, pad;
+};
+
+__host__ __device__ inline OutcomeConst make_outcome_const(const Model &P) {
+  OutcomeConst o;
+  o.v_frag = P.v_frag;
+  o.erosion_ratio = P.erosion_ratio;
+  o.erosion_chi = P.erosion_chi;
+  o.m0 = P.m0;
+  o.dm_max = P.dm_max;
+  o.frag_width = P.frag_width;
+  o.kernel = P.kernel;
+  o.frag_mode = P.frag_mode;
+  o.n_comp = P.n_comp;
+  o.pad = 0;
+  return o;
+}
+
 struct DiskPoint {
   double Sigma_g, T, cs, Omega, H, rho_g;
 };
@@ -472,7 +495,8 @@ __host__ __device__ inline double frag_draw(double lo, double hi, double u) {
 // erodes): linear ramp from (1 - w) v_frag to v_frag, or the tail above
 // v_frag of the Maxwell speed distribution with mean dv (scale a =
 // dv sqrt(pi/8)): erfc(x) + 2/sqrt(pi) x exp(-x^2), x = v_frag / (sqrt(2) a)
-__host__ __device__ inline double frag_probability(const Model &P, double dv) {
+template <typename PP>
+__host__ __device__ inline double frag_probability(const PP &P, double dv) {
   const double vf = P.v_frag;
   if (P.frag_mode == FRAG_RAMP) {
     const double lo = (1.0 - P.frag_width) * vf;
@@ -497,7 +521,8 @@ __host__ __device__ inline double group_factor(double dm_max, double mi, double 
 
 // collision outcome for representative particle i (mass mi) hitting a body
 // of swarm j (mass mj) at relative velocity dv; returns the outcome code
-__host__ __device__ inline int outcome(const Model &P, bool fast, double mi, double mj, double u,
+template <typename PP>
+__host__ __device__ inline int outcome(const PP &P, bool fast, double mi, double mj, double u,
                                        double &m_new) {
   const double grp = group_factor(P.dm_max, mi, mj);
   if (P.kernel != K_PHYSICAL || !fast) {
