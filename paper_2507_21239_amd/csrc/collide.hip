@@ -345,7 +345,7 @@ __device__ inline int event_outcome(const CollideArgs &A, const TeamScratch *S, 
   } else {
     fast = !(dvj < (RT)P.v_frag);
   }
-  const int oc = outcome(P, fast, mi, mj, u4, mnew);
+  const int oc = outcome<sizeof(RT) == 8>(P, fast, mi, mj, u4, mnew);
   if (writer) {
     if ((!(mnew > 0.0) || !isfinite(mnew)) && lane == 0) atomicOr(&A.state->flags, FLAG_BAD_MASS);
     if (A.comp != nullptr && P.n_comp > 0 && (oc == OUT_STICK || oc == OUT_FRAG) &&
@@ -360,9 +360,9 @@ __device__ inline int event_outcome(const CollideArgs &A, const TeamScratch *S, 
   return oc;
 }
 
-__device__ inline void log_event(const CollideArgs &A, int cell, int64_t e, int i_local,
+__device__ inline void log_event(const CollideArgs &A, int cell, uint32_t e, int i_local,
                                  int j_local, int oc) {
-  if (A.evlog != nullptr && e < A.log_per_cell) {
+  if (A.evlog != nullptr && (int64_t)e < A.log_per_cell) {
     int32_t *L = A.evlog + ((size_t)cell * A.log_per_cell + e) * 4;
     L[0] = i_local;
     L[1] = j_local;
@@ -494,10 +494,11 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
 
   // ---- events ------------------------------------------------------------
   double t = 0.0;
-  int64_t e = 0;
+  uint32_t e = 0;  // events so far (fewer than 2^32 per cell and step)
   uint32_t oc_count[4] = {0u, 0u, 0u, 0u};
   const uint32_t c32 = (uint32_t)cell;
   const bool timed = A.dt > 0.0;
+  const uint32_t emax = A.max_events > 0 ? (uint32_t)A.max_events : 0xFFFFFFFFu;
   double part = 0.0, Rtot;
 #pragma unroll
   for (int q = 0; q < KMAX; ++q)
@@ -510,7 +511,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
   // uniforms of 64 consecutive events: lane l holds -ln u1, u2, u3, u4 of
   // event e0 + l from Philox(e0 + l, cell, step, 0) and (.., 1)
   double nlu1 = 0.0, uu2 = 0.0, uu3 = 0.0, uu4 = 0.0;
-  int64_t e0 = -64;
+  uint32_t e0 = 0u - 64u;  // first event of the current batch (none yet)
   const int K_cell = K;
   for (;;) {
     // K per event: tests of q < K are made where they are needed instead of
@@ -520,7 +521,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
       if (!isfinite(Rtot) && tl == 0) atomicOr(&A.state->flags, FLAG_BAD_RATE);
       break;
     }
-    if (A.max_events > 0 && e >= A.max_events) break;
+    if (e >= emax) break;
     if (e - e0 >= 64) {
       e0 = e;
       const uint32_t ec = (uint32_t)(e + lane);
@@ -597,7 +598,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     double mnew = 0.0;
     Rec<RT> rin;
     const int oc = event_outcome<RT, PROB>(A, tm.S, mi, cj.p0, Mi, (RT)cj.p1, readlane_d(uu4, rl), gi,
-                                     cj.gi, lane, wave == 0, (uint32_t)e, c32, step, mnew, rin);
+                                     cj.gi, lane, wave == 0, e, c32, step, mnew, rin);
     if (tl == 0) log_event(A, cell, e, i_local, cj.lane * K + cj.q, oc);
     // the owner of i keeps the new mass and record; it alone reads the slot
     // until the next exchange

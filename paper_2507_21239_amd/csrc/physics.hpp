@@ -520,20 +520,33 @@ __host__ __device__ inline double group_factor(double dm_max, double mi, double 
 }
 
 // collision outcome for representative particle i (mass mi) hitting a body
-// of swarm j (mass mj) at relative velocity dv; returns the outcome code
-template <typename PP>
+// of swarm j (mass mj) at relative velocity dv; returns the outcome code.
+// EXACT: the grouped mass grp * mj and the mass-ratio test as written (the
+// FP64 path); otherwise their division-free equivalents max(mj, dm_max mi)
+// and big >= ratio * small, equal up to one rounding (the mixed path)
+template <bool EXACT = true, typename PP>
 __host__ __device__ inline int outcome(const PP &P, bool fast, double mi, double mj, double u,
                                        double &m_new) {
-  const double grp = group_factor(P.dm_max, mi, mj);
+  // grouped mass grp * mj; the eroded mass chi grp mj
+  double gm, em;
+  if (EXACT) {
+    const double grp = group_factor(P.dm_max, mi, mj);
+    gm = grp * mj;
+    em = P.erosion_chi * grp * mj;
+  } else {
+    const double d = P.dm_max * mi;
+    gm = (P.dm_max > 0.0 && d > mj) ? d : mj;
+    em = P.erosion_chi * gm;
+  }
   if (P.kernel != K_PHYSICAL || !fast) {
-    m_new = mi + grp * mj;
+    m_new = mi + gm;
     return OUT_STICK;
   }
   const double big = mi > mj ? mi : mj;
   const double small = mi > mj ? mj : mi;
-  if (big / small >= P.erosion_ratio) {
+  if (EXACT ? big / small >= P.erosion_ratio : big >= P.erosion_ratio * small) {
     if (mi >= mj) {
-      const double m = mi - P.erosion_chi * grp * mj;
+      const double m = mi - em;
       m_new = m > P.m0 ? m : P.m0;
       return OUT_ERODE;
     }
