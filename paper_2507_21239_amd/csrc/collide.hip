@@ -512,11 +512,14 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
   // event e0 + l from Philox(e0 + l, cell, step, 0) and (.., 1)
   double nlu1 = 0.0, uu2 = 0.0, uu3 = 0.0, uu4 = 0.0;
   uint32_t e0 = 0u - 64u;  // first event of the current batch (none yet)
-  const int K_cell = K;
+  const int K_cell = K, lane_cell = lane, wave_cell = wave;
   for (;;) {
-    // K per event: tests of q < K are made where they are needed instead of
-    // being kept as lane masks across the loop
+    // K and the lane / wave indices per event: tests such as q < K, w < wave
+    // or lane == 63 are made where they are needed instead of being kept as
+    // lane masks across the loop
     const int K = opaque_s(K_cell);
+    tm.lane = opaque_v(lane_cell);
+    tm.wave = opaque_s(wave_cell);
     if (!(Rtot > 0.0) || !isfinite(Rtot)) {
       if (!isfinite(Rtot) && tl == 0) atomicOr(&A.state->flags, FLAG_BAD_RATE);
       break;

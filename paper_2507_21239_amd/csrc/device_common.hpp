@@ -84,6 +84,13 @@ __device__ inline T opaque_s(T x) {
   asm volatile("" : "+s"(x));
   return x;
 }
+// the same for a per-lane 32-bit value (kept in a vector register)
+template <typename T>
+__device__ inline T opaque_v(T x) {
+  static_assert(sizeof(T) == 4, "32-bit values");
+  asm volatile("" : "+v"(x));
+  return x;
+}
 
 // inclusive prefix sum over the 64 lanes: shifts of 1, 2, 4, 8 inside rows of
 // 16 lanes, then row broadcasts of lanes 15 and 31 (gfx9 DPP)
