@@ -153,11 +153,13 @@ struct Team {
     total = tot;
     return off + inc;
   }
-  // team-inclusive prefix of a plus the totals of a and b (one exchange)
-  __device__ double scan2(double a, double b, double &tot_a, double &tot_b) {
+  // team-inclusive prefix of a plus the totals of a and b (one exchange); b
+  // is summed over each wave in its own precision (BT), then in FP64
+  template <typename BT>
+  __device__ double scan2(double a, BT b, double &tot_a, double &tot_b) {
     const double ia = wave_incl_scan(a);
-    const double ib = wave_incl_scan(b);
-    const double wa = readlane_d(ia, 63), wb = readlane_d(ib, 63);
+    const BT ib = wave_incl_scan(b);
+    const double wa = readlane_d(ia, 63), wb = (double)readlane_t(ib, 63);
     if (nw == 1) {
       tot_a = wa;
       tot_b = wb;
@@ -613,7 +615,9 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     }
 
     // -- new row i: incremental update of the other rows, fresh row sum of i
-    double part2 = 0.0;
+    // the fresh row sum of i: in the rate precision within a wave (the FP32
+    // tree adds no more than the rates' own rounding), then FP64
+    RT part2 = (RT)0;
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) {
       if (q < K) {
@@ -621,7 +625,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
         const Rec<RT> rq = R.load(s);
         RT dv, a_iq, a_qi;
         PairEval<RT, FAST>::run(pc, rin, rq, dv, a_iq, a_qi);
-        part2 += (double)a_iq;
+        part2 += a_iq;
         const double x = (r[q] - (double)rji[q]) + (double)a_qi;
         const bool upd = s != si && ((valid >> q) & 1u);
         r[q] = upd ? (x > 0.0 ? x : 0.0) : r[q];

@@ -73,6 +73,10 @@ __device__ inline double readlane_d(double x, int lane) {
 }
 
 __device__ inline int readlane_i(int x, int lane) { return __builtin_amdgcn_readlane(x, lane); }
+__device__ inline float readlane_t(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+__device__ inline double readlane_t(double x, int lane) { return readlane_d(x, lane); }
 
 // a wave-uniform 32-bit value returned unchanged but hidden from the
 // optimizer: what is derived from it is recomputed where it is used rather
@@ -92,8 +96,23 @@ __device__ inline T opaque_v(T x) {
   return x;
 }
 
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ inline float dpp_f(float x) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, BANK_MASK, true));
+}
+
 // inclusive prefix sum over the 64 lanes: shifts of 1, 2, 4, 8 inside rows of
 // 16 lanes, then row broadcasts of lanes 15 and 31 (gfx9 DPP)
+__device__ inline float wave_incl_scan(float x) {
+  x += dpp_f<0x111, 0xf, 0xf>(x);  // row_shr:1
+  x += dpp_f<0x112, 0xf, 0xf>(x);  // row_shr:2
+  x += dpp_f<0x114, 0xf, 0xf>(x);  // row_shr:4
+  x += dpp_f<0x118, 0xf, 0xf>(x);  // row_shr:8
+  x += dpp_f<0x142, 0xa, 0xf>(x);  // row_bcast:15 into rows 1, 3
+  x += dpp_f<0x143, 0xc, 0xf>(x);  // row_bcast:31 into rows 2, 3
+  return x;
+}
 __device__ inline double wave_incl_scan(double x) {
   x += dpp_d<0x111, 0xf, 0xf>(x);  // row_shr:1
   x += dpp_d<0x112, 0xf, 0xf>(x);  // row_shr:2

@@ -431,7 +431,8 @@ __device__ inline void pair_rates_all(const PairConst<float> &c, const Rec<float
   const bool xb = x.St > y.St;
   const float St1 = xb ? x.St : y.St;
   const float ist1 = xb ? x.ist : y.ist;
-  const float hd = xb ? x.h - y.h : y.h - x.h;
+  // h = St^2 / (St + St_eta) grows with St: the larger-St particle has the larger h
+  const float hd = fabsf(x.h - y.h);
   const float eps = (xb ? y.St : x.St) * ist1;
   const float ye = ya + eps;
   const float rd = __builtin_amdgcn_rcpf((1.0f + eps) * ye);
