@@ -108,6 +108,75 @@ struct PairEval<float, true> {
 };
 
 // ---------------------------------------------------------------------------
+// row sums of a one-wave FP32 cell, each unordered pair evaluated once
+// ---------------------------------------------------------------------------
+// Lane l holds slots (q, l), q < K.  Step 0 pairs the lane's own slots; step
+// d = 1..32 pairs lane l with lane (l + d) mod 64 (at d = 32 only lanes below
+// 32 evaluate, so every pair of lanes meets once).  r_xy goes to the lane's
+// own sums; r_yx to an accumulator of the partner lane's sums that moves one
+// lane down after every step (DPP wave rotation), so that the accumulator of
+// lane X is always held by the lane currently paired with X; after step 32 it
+// sits at lane X - 32 and returns with one exchange of the wave's halves.
+// Sums are in FP32, in an order that differs from the canonical one; slots
+// past the cell's particles get 0.
+template <int KMAX>
+__device__ inline void build_rows_pairwise(const RecStore<float> &R, const PairConst<float> &pc,
+                                           int K, int lane, int n, double r[KMAX]) {
+  Rec<float> mine[KMAX];
+  float acc[KMAX], pacc[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    acc[q] = 0.0f;
+    pacc[q] = 0.0f;
+    if (q < K) mine[q] = R.load(q * 64 + lane);
+  }
+#pragma unroll
+  for (int I = 0; I < KMAX; ++I) {
+#pragma unroll
+    for (int J = I; J < KMAX; ++J) {
+      if (J < K) {
+        float dv, rxy, ryx;
+        pair_rates_all(pc, mine[I], mine[J], dv, rxy, ryx);
+        acc[I] += rxy;
+        if (J != I) acc[J] += ryx;
+      }
+    }
+  }
+#pragma unroll 1
+  for (int d = 1; d <= 32; ++d) {
+    const int c = (lane + d) & 63;
+    Rec<float> pr[KMAX];
+#pragma unroll
+    for (int J = 0; J < KMAX; ++J)
+      if (J < K) pr[J] = R.load(J * 64 + c);
+    const bool take = d < 32 || lane < 32;
+#pragma unroll
+    for (int I = 0; I < KMAX; ++I) {
+#pragma unroll
+      for (int J = 0; J < KMAX; ++J) {
+        if (I < K && J < K) {
+          float dv, rxy, ryx;
+          pair_rates_all(pc, mine[I], pr[J], dv, rxy, ryx);
+          acc[I] += take ? rxy : 0.0f;
+          pacc[J] += take ? ryx : 0.0f;
+        }
+      }
+    }
+    if (d < 32) {
+#pragma unroll
+      for (int J = 0; J < KMAX; ++J)  // lane l takes lane l + 1's accumulators
+        pacc[J] = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(pacc[J]), 0x134,
+                                                             0xf, 0xf, false));
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    const float home = __shfl_xor(pacc[q], 32, 64);
+    r[q] = (q < K && lane * K + q < n) ? (double)(acc[q] + home) : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // team: nw waves of one workgroup, runtime size
 // ---------------------------------------------------------------------------
 struct Team {
@@ -453,12 +522,20 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
   }
   tm.sync();
 
-  // ---- row sums r_i = sum_k r_ik, k in canonical order ------------------
-  // Partners k = 0..n-1 are read once per group of G own slots and paired
-  // with each of them (independent evaluations); each row still adds its
-  // terms in canonical order.
+  // ---- row sums r_i = sum_k r_ik ------------------------------------------
+  // One-wave cells of the FP32 form evaluate each unordered pair once
+  // (build_rows_pairwise).  Otherwise partners k = 0..n-1 are read once per
+  // group of G own slots and paired with each of them (independent
+  // evaluations), and each row adds its terms in canonical order.
   double r[KMAX];
-  {
+  bool built = false;
+  if constexpr (sizeof(RT) == 4 && FAST && KMAX == 4) {
+    if (nw == 1) {
+      build_rows_pairwise<KMAX>(R, pc, K, lane, n, r);
+      built = true;
+    }
+  }
+  if (!built) {
     constexpr int G = sizeof(RT) == 4 ? 4 : 2;
     static_assert(KMAX % G == 0, "slot groups");
 #pragma unroll
