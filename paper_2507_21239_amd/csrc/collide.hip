@@ -176,6 +176,123 @@ __device__ inline void build_rows_pairwise(const RecStore<float> &R, const PairC
   }
 }
 
+// Four-wave FP32 teams: the same scheme over the team's 256 lanes.  Wave a
+// first pairs its own lanes as above; then in phases p = 1..3 it pairs lane
+// l with lane (l + d) mod 64 of wave b = (a + p) mod 4, for d = 0..31 if
+// a < b and d = 1..32 if a > b (the two waves of a pair split the 64 lane
+// offsets between them).  After each phase the partner accumulators, which
+// moved one lane per step as above, go to wave b through the exchange buffer
+// in two rounds of two slots (a barrier after each write and before reuse).
+template <int KMAX>
+__device__ inline void build_rows_pairwise_team(const RecStore<float> &R, const PairConst<float> &pc,
+                                                int K, int wave, int lane, int n, float2 *xbuf,
+                                                double r[KMAX]) {
+  static_assert(KMAX % 2 == 0, "partner sums go over in pairs of slots");
+  constexpr int TL = 256;
+  const int own = wave * 64;
+  Rec<float> mine[KMAX];
+  float acc[KMAX], pacc[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    acc[q] = 0.0f;
+    pacc[q] = 0.0f;
+    if (q < K) mine[q] = R.load(q * TL + own + lane);
+  }
+#pragma unroll
+  for (int I = 0; I < KMAX; ++I) {
+#pragma unroll
+    for (int J = I; J < KMAX; ++J) {
+      if (J < K) {
+        float dv, rxy, ryx;
+        pair_rates_all(pc, mine[I], mine[J], dv, rxy, ryx);
+        acc[I] += rxy;
+        if (J != I) acc[J] += ryx;
+      }
+    }
+  }
+  // the other lanes of the own wave
+#pragma unroll 1
+  for (int d = 1; d <= 32; ++d) {
+    const int c = (lane + d) & 63;
+    Rec<float> pr[KMAX];
+#pragma unroll
+    for (int J = 0; J < KMAX; ++J)
+      if (J < K) pr[J] = R.load(J * TL + own + c);
+    const bool take = d < 32 || lane < 32;
+#pragma unroll
+    for (int I = 0; I < KMAX; ++I) {
+#pragma unroll
+      for (int J = 0; J < KMAX; ++J) {
+        if (I < K && J < K) {
+          float dv, rxy, ryx;
+          pair_rates_all(pc, mine[I], pr[J], dv, rxy, ryx);
+          acc[I] += take ? rxy : 0.0f;
+          pacc[J] += take ? ryx : 0.0f;
+        }
+      }
+    }
+    if (d < 32) {
+#pragma unroll
+      for (int J = 0; J < KMAX; ++J)
+        pacc[J] = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(pacc[J]), 0x134,
+                                                             0xf, 0xf, false));
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    acc[q] += __shfl_xor(pacc[q], 32, 64);
+    pacc[q] = 0.0f;
+  }
+  // the lanes of the other three waves
+#pragma unroll 1
+  for (int p = 1; p <= 3; ++p) {
+    const int b = (wave + p) & 3;
+    const int d0 = wave < b ? 0 : 1;
+#pragma unroll 1
+    for (int st = 0; st < 32; ++st) {
+      const int c = (lane + d0 + st) & 63;
+      Rec<float> pr[KMAX];
+#pragma unroll
+      for (int J = 0; J < KMAX; ++J)
+        if (J < K) pr[J] = R.load(J * TL + b * 64 + c);
+#pragma unroll
+      for (int I = 0; I < KMAX; ++I) {
+#pragma unroll
+        for (int J = 0; J < KMAX; ++J) {
+          if (I < K && J < K) {
+            float dv, rxy, ryx;
+            pair_rates_all(pc, mine[I], pr[J], dv, rxy, ryx);
+            acc[I] += rxy;
+            pacc[J] += ryx;
+          }
+        }
+      }
+      if (st < 31) {
+#pragma unroll
+        for (int J = 0; J < KMAX; ++J)
+          pacc[J] = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(pacc[J]), 0x134,
+                                                               0xf, 0xf, false));
+      }
+    }
+    // lane l now holds the sums of lane (l + d0 + 31) mod 64 of wave b; they
+    // go over in two rounds of two slots
+#pragma unroll
+    for (int h = 0; h < KMAX; h += 2) {
+      xbuf[b * 64 + ((lane + d0 + 31) & 63)] = make_float2(pacc[h], pacc[h + 1]);
+      block_lds_sync();
+      const float2 in = xbuf[own + lane];
+      acc[h] += in.x;
+      acc[h + 1] += in.y;
+      block_lds_sync();
+    }
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) pacc[q] = 0.0f;
+  }
+  const int tl = own + lane;
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) r[q] = (q < K && tl * K + q < n) ? (double)acc[q] : 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // team: nw waves of one workgroup, runtime size
 // ---------------------------------------------------------------------------
@@ -523,17 +640,19 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
   tm.sync();
 
   // ---- row sums r_i = sum_k r_ik ------------------------------------------
-  // One-wave cells of the FP32 form evaluate each unordered pair once
-  // (build_rows_pairwise).  Otherwise partners k = 0..n-1 are read once per
+  // The FP32 form evaluates each unordered pair once (build_rows_pairwise,
+  // build_rows_pairwise_team).  Otherwise partners k = 0..n-1 are read once per
   // group of G own slots and paired with each of them (independent
   // evaluations), and each row adds its terms in canonical order.
   double r[KMAX];
   bool built = false;
   if constexpr (sizeof(RT) == 4 && FAST && KMAX == 4) {
-    if (nw == 1) {
+    if (nw == 1)
       build_rows_pairwise<KMAX>(R, pc, K, lane, n, r);
-      built = true;
-    }
+    else
+      build_rows_pairwise_team<KMAX>(R, pc, K, wave, lane, n,
+                                     (float2 *)(base + xbuf_offset<RT>(cap)), r);
+    built = true;
   }
   if (!built) {
     constexpr int G = sizeof(RT) == 4 ? 4 : 2;

@@ -71,10 +71,23 @@ constexpr size_t rec_bytes() {
   return 12 * sizeof(RT);
 }
 
-// LDS bytes of one team region holding `cap` particles (16-byte multiple)
+// partner-sum exchange of a four-wave FP32 team's row-sum build:
+// [wave][lane] pairs of floats (two slots per round), after the team scratch.
+// 2 KB keeps a 1024-particle team region within the LDS of four 256-particle
+// one-wave regions, so the exchange costs no occupancy
+constexpr size_t kXbufBytes = 4 * 64 * 2 * sizeof(float);
+
+// byte offset of the exchange buffer in a team region holding `cap` particles
 template <typename RT>
-constexpr size_t region_bytes(int cap, int /*waves*/) {
+constexpr size_t xbuf_offset(int cap) {
   return ((size_t)cap * rec_bytes<RT>() + sizeof(TeamScratch) + 15) / 16 * 16;
+}
+
+// LDS bytes of one team region holding `cap` particles (16-byte multiple);
+// four-wave FP32 teams add the exchange buffer
+template <typename RT>
+constexpr size_t region_bytes(int cap, int waves) {
+  return xbuf_offset<RT>(cap) + (sizeof(RT) == 4 && waves == 4 ? kXbufBytes : 0);
 }
 
 // launchers (collide.hip)
