@@ -178,10 +178,13 @@ mcd_status mcd_bin(mcd_ctx *ctx, const mcd_cells *explicit_or_null);
 
 /* Rate matrix of one cell (test path): r_out[i*ld + j] = r_ij, the rate at
  * which representative particle i collides with a body of swarm j, computed
- * by the same code as the collision kernel in the context's precision and
- * returned as FP64 (device pointer, n_c x n_c with leading dimension ld >=
- * n_c); rowsum_out[i] = sum_j r_ij as the collision kernel starts from
- * (device, may be NULL).  Synchronises.  MCD_EINVAL if cell is out of range. */
+ * by the same pair code as the collision kernel in the context's precision
+ * and returned as FP64 (device pointer, n_c x n_c with leading dimension ld
+ * >= n_c); rowsum_out[i] = sum_j r_ij in canonical order j = 0..n_c-1
+ * (device, may be NULL).  In FP64 these are the collision kernel's starting
+ * row sums; the FP32 form's kernel adds the same terms in another order
+ * (each unordered pair once), equal up to FP32 rounding.  Synchronises.
+ * MCD_EINVAL if cell is out of range. */
 mcd_status mcd_rates(mcd_ctx *ctx, int32_t cell, double *r_out, int64_t ld, double *rowsum_out);
 
 /* Advance n_steps global steps of length dt [s]: (re)bin when the grid is
