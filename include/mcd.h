@@ -18,8 +18,10 @@
  *    non-owning views and never frees them.  They must outlive the context.
  *  - All device work is enqueued on the caller's HIP stream given to
  *    mcd_init; functions marked "async" return before the work completes.
- *  - The library allocates its own device workspace in mcd_init / mcd_bin
- *    (hipMalloc) and frees it in mcd_free.
+ *  - The library allocates its own device workspace (hipMalloc): in mcd_init
+ *    and mcd_bin, and on first use in mcd_tune, mcd_set_gas_grid,
+ *    mcd_sigma_hist and mcd_snapshot.  mcd_step allocates nothing.  mcd_free
+ *    frees it all.
  *  - Every function returns an mcd_status; no C++ exception crosses the ABI.
  *    After an error, mcd_last_error(ctx) describes it.  Kernels that detect
  *    an anomaly (a NaN or infinite rate, a non-positive mass or volume) set a
@@ -69,7 +71,7 @@ typedef enum {
                        masses, prefix sums, row-sum state and time in FP64 */
 
 /* cell schedule of the collision kernel */
-#define MCD_SCHED_PLAIN 0   /* one one-wave workgroup per cell, launched per step */
+#define MCD_SCHED_PLAIN 0   /* one four-wave workgroup per cell, launched per step */
 #define MCD_SCHED_BATCHED 1 /* one persistent launch: big cells largest-first on
                                four-wave teams, small cells on single waves;
                                multi-step loops replayed from a HIP graph */
