@@ -180,6 +180,101 @@ def full_step(steps, warmup):
             "bin_ms": bin_ms, "tuned_schedule": tuned}
 
 
+def next_rows(steps, warmup):
+    """Cost of the NEXT rows, measured on the workloads they serve (mixed, batched,
+    fixed schedule 256,0 so that no tuning trials enter the timings):
+    - the large disk's whole step with the power-law gas and with a gridded gas
+      (48 x 24 nodes; the gas is sampled per cell, per particle in transport and
+      once per cell for eta v_K);
+    - the batched workload's collision step with the sharp fragmentation
+      criterion and with the ramp and Maxwell criteria (their kernel variant);
+    - the large disk's step with an asynchronous snapshot of (r, z, m, active,
+      comp) after every step, against none;
+    - one sigma_d(m, r) histogram of the large disk, 60 radial x 64 mass bins."""
+    import numpy as np
+    import torch
+    from paper_2507_21239_amd import api
+    from paper_2507_21239_amd import workloads as W
+
+    def timed(sim, run):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a.record()
+        run()
+        b.record()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, a.elapsed_time(b)
+
+    def disk(gas_grid=None, snapshot=False):
+        work = W.c5_large_disk(seed=0)
+        dev = api.to_device(work["particles"])
+        sim = api.Simulation(work["params"], dev, precision="mixed", schedule="batched")
+        if gas_grid is not None:
+            sim.set_gas_grid(gas_grid)
+        sim.bin()
+        sim.set_schedule(256, 0)
+        sim.step(W.YR, 0, max(warmup, 2))
+        bufs, snaps = [], []
+        if snapshot:
+            # a first snapshot sizes the library's staging; then two rotating pinned buffers
+            first = sim.snapshot()
+            first.wait()
+            bufs = [torch.empty_like(first.buf, pin_memory=True) for _ in range(2)]
+
+        def run():
+            if not snapshot:
+                sim.step(W.YR, 0, steps)
+                return
+            for k in range(steps):
+                sim.step(W.YR, 0, 1)
+                if len(snaps) == 2:
+                    snaps.pop(0).wait()
+                snaps.append(sim.snapshot(out=bufs[k % 2]))
+            for sn in snaps:
+                sn.wait()
+        wall, gpu = timed(sim, run)
+        sim.close()
+        return {"ms_per_step": wall / steps, "gpu_ms_per_step": gpu / steps}
+
+    def c4(frag_mode):
+        work = W.c4_batched(seed=0, events=EVENTS_PER_CELL)
+        p = dict(work["params"])
+        p["frag_mode"] = frag_mode
+        dev = api.to_device(work["particles"])
+        sim = api.Simulation(p, dev, precision="mixed", schedule="batched")
+        sim.bin(api.cells_to_device(work["cells"]))
+        sim.set_schedule(256, 0)
+        sim.step(0.0, EVENTS_PER_CELL, max(warmup, 2))
+        wall, gpu = timed(sim, lambda: sim.step(0.0, EVENTS_PER_CELL, steps))
+        out = sim.stats()["outcomes"]
+        sim.close()
+        return {"ms_per_step": wall / steps, "outcomes_since_init": [int(x) for x in out]}
+
+    res = {}
+    log("next rows: large disk, power-law gas")
+    res["disk_power_law"] = disk()
+    log("next rows: large disk, gridded gas")
+    res["disk_gridded_gas"] = disk(gas_grid=W.gridded_gas(W.c5_large_disk(seed=0)["params"]))
+    log("next rows: large disk, snapshot after every step")
+    res["disk_snapshot_every_step"] = disk(snapshot=True)
+    for mode in ("sharp", "ramp", "maxwell"):
+        log("next rows: batched workload, fragmentation", mode)
+        res[f"c4_frag_{mode}"] = c4(mode)
+    log("next rows: sigma_d histogram")
+    work = W.c5_large_disk(seed=0)
+    dev = api.to_device(work["particles"])
+    sim = api.Simulation(work["params"], dev, precision="mixed", schedule="batched")
+    re = W.AU * np.logspace(0.0, 2.0, 61)
+    me = np.logspace(-14.0, 4.0, 65)
+    sim.sigma_hist(re, me)
+    reps = 10
+    wall, gpu = timed(sim, lambda: [sim.sigma_hist(re, me) for _ in range(reps)])
+    sim.close()
+    res["sigma_hist_60x64"] = {"ms": gpu / reps, "particles": len(work["particles"]["m"])}
+    return res
+
+
 def copy_calibration():
     import torch
     x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -353,7 +448,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-error", action="store_true", help="skip the error report")
     ap.add_argument("--modes", default="all",
-                    help="all | headline | none (none: only the full step, for profiling)")
+                    help="all | headline | none (only the full step, for profiling) | "
+                         "next (cost of the NEXT rows)")
     ap.add_argument("--no-full-step", action="store_true", help="skip the full-path measurement")
     ap.add_argument("--schedule", default=None,
                     help="SMALL_MAX,GRID_PER_CU: fixed batched schedule instead of the autotuner "
@@ -384,6 +480,10 @@ def main():
     evals = pair_evals(counts, EVENTS_PER_CELL)
     log("workload", len(counts), "cells", int(counts.sum()), "particles", f"{evals:.3e} pair evals/step")
 
+    if args.modes == "next":
+        print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
+                          "next_rows": next_rows(args.steps, args.warmup)}), flush=True)
+        return
     if args.modes == "none":
         fs = full_step(args.steps, args.warmup)
         print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",

@@ -518,18 +518,18 @@ __device__ inline Cand team_pick(Team &tm, double incl, double part, const VT *v
 // mass-weighted composition of i on sticking or fragmentation (lanes below
 // n_comp, one component each).
 // PROB: the probabilistic fragmentation criteria (a kernel variant of its
-// own, so that the sharp criterion carries none of their FP64 special
-// functions); their uniform comes from Philox (e, cell, step, 3)
+// own, so that the sharp criterion carries none of their special functions);
+// u5 is their uniform, from Philox (e, cell, step, 3).  The FP64 form takes
+// the probability in FP64; the mixed form, whose relative velocity is FP32,
+// in FP32
 template <typename RT, bool PROB>
 __device__ inline int event_outcome(const CollideArgs &A, const TeamScratch *S, double mi,
-                                    double mj, double Mi, RT dvj, double u4, int gi, int gj,
-                                    int lane, bool writer, uint32_t e, uint32_t cell,
-                                    uint32_t step, double &mnew, Rec<RT> &rin) {
+                                    double mj, double Mi, RT dvj, double u4, double u5, int gi,
+                                    int gj, int lane, bool writer, double &mnew, Rec<RT> &rin) {
   const OutcomeConst &P = S->oc;
   bool fast;
   if constexpr (PROB) {
-    const U4 w = philox4x32_10(U4{e, cell, step, 3u}, A.P.key0, A.P.key1);
-    fast = u01(w.x, w.y) < frag_probability(P, (double)dvj);
+    fast = u5 < (double)frag_probability(P, dvj);
   } else {
     fast = !(dvj < (RT)P.v_frag);
   }
@@ -708,7 +708,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
   double delta = 0.0;
   // uniforms of 64 consecutive events: lane l holds -ln u1, u2, u3, u4 of
   // event e0 + l from Philox(e0 + l, cell, step, 0) and (.., 1)
-  double nlu1 = 0.0, uu2 = 0.0, uu3 = 0.0, uu4 = 0.0;
+  double nlu1 = 0.0, uu2 = 0.0, uu3 = 0.0, uu4 = 0.0, uu5 = 0.0;
   uint32_t e0 = 0u - 64u;  // first event of the current batch (none yet)
   const int K_cell = K, lane_cell = lane, wave_cell = wave;
   for (;;) {
@@ -734,6 +734,10 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
       uu2 = u01(w0.z, w0.w);
       uu3 = u01(w1.x, w1.y);
       uu4 = u01(w1.z, w1.w);
+      if constexpr (PROB) {  // the fragmentation uniform u5
+        const U4 w3 = philox4x32_10(U4{ec, c32, step, 3u}, k0, k1);
+        uu5 = u01(w3.x, w3.y);
+      }
     }
     const int rl = (int)(e - e0);
     if (timed) {
@@ -798,8 +802,9 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
                                     m64, dvv, gix);
     double mnew = 0.0;
     Rec<RT> rin;
-    const int oc = event_outcome<RT, PROB>(A, tm.S, mi, cj.p0, Mi, (RT)cj.p1, readlane_d(uu4, rl), gi,
-                                     cj.gi, lane, wave == 0, e, c32, step, mnew, rin);
+    const int oc = event_outcome<RT, PROB>(A, tm.S, mi, cj.p0, Mi, (RT)cj.p1, readlane_d(uu4, rl),
+                                           PROB ? readlane_d(uu5, rl) : 0.0, gi, cj.gi, lane,
+                                           wave == 0, mnew, rin);
     if (tl == 0) log_event(A, cell, e, i_local, cj.lane * K + cj.q, oc);
     // the owner of i keeps the new mass and record; it alone reads the slot
     // until the next exchange

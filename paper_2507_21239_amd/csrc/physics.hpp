@@ -496,21 +496,22 @@ __host__ __device__ inline double frag_draw(double lo, double hi, double u) {
 // erodes): linear ramp from (1 - w) v_frag to v_frag, or the tail above
 // v_frag of the Maxwell speed distribution with mean dv (scale a =
 // dv sqrt(pi/8)): erfc(x) + 2/sqrt(pi) x exp(-x^2), x = v_frag / (sqrt(2) a)
-template <typename PP>
-__host__ __device__ inline double frag_probability(const PP &P, double dv) {
-  const double vf = P.v_frag;
+// in the precision T of dv (double for the FP64 form, float for the mixed one)
+template <typename PP, typename T>
+__host__ __device__ inline T frag_probability(const PP &P, T dv) {
+  const T vf = (T)P.v_frag;
   if (P.frag_mode == FRAG_RAMP) {
-    const double lo = (1.0 - P.frag_width) * vf;
-    if (dv <= lo) return 0.0;
-    if (dv >= vf) return 1.0;
+    const T lo = ((T)1 - (T)P.frag_width) * vf;
+    if (dv <= lo) return (T)0;
+    if (dv >= vf) return (T)1;
     return (dv - lo) / (vf - lo);
   }
   if (P.frag_mode == FRAG_MAXWELL) {
-    if (!(dv > 0.0)) return 0.0;
-    const double x = 2.0 * vf / (sqrt(kPi) * dv);
-    return erfc(x) + 2.0 / sqrt(kPi) * x * exp(-x * x);
+    if (!(dv > (T)0)) return (T)0;
+    const T x = (T)2 * vf / (sqrt((T)kPi) * dv);
+    return erfc(x) + (T)2 / sqrt((T)kPi) * x * exp(-x * x);
   }
-  return dv < vf ? 0.0 : 1.0;
+  return dv < vf ? (T)0 : (T)1;
 }
 
 // grouping factor max(1, dm_max m_i / m_j)
