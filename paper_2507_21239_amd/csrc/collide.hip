@@ -19,7 +19,9 @@
 // indexed by s = q*64nw + t (slot q of lane t), so a wave reads consecutive
 // 16-byte words.  Row sums (FP64), the per-event row values, masses and
 // particle indices stay in registers of the owning lane; masses go back to
-// HBM once, when the cell is done.
+// HBM once, when the cell is done.  In the FP32 form the starting row sums
+// evaluate each unordered pair once (build_rows_pairwise*); the FP64 form
+// sums every row in canonical order.
 #include <algorithm>
 
 #include "device_common.hpp"
