@@ -373,24 +373,24 @@ __global__ __launch_bounds__(256) void k_keys_zone(const int32_t *__restrict__ v
 // ---------------------------------------------------------------------------
 // order of each zone by (z, index): one workgroup per zone runs a bitonic
 // network over the zone padded to P = 8 x threads (a power of two, >= 512).
-// Thread t keeps positions 8t .. 8t+7 in registers: strides below 8 compare
-// inside a thread, strides 8 .. 256 pair lanes of one wave (shuffles, no
+// The key of an element packs its z bit pattern, range-reduced to 32 bits
+// over the zone ((bits - min) >> shift), above its 32-bit particle index, so
+// that one 64-bit comparison orders (reduced z, index).  Thread t keeps
+// positions 8t .. 8t+7 in registers: strides below 8 compare inside a
+// thread, strides 8 .. 256 pair lanes of one wave (DPP and permutes, no
 // barrier), strides of 512 and up exchange through LDS between barriers.
+// When shift > 0 distinct z can share a reduced key; each run of equal
+// reduced keys is then re-sorted by (full bits, index), so the result is the
+// exact (z, index) order.
 // ---------------------------------------------------------------------------
 constexpr int kZoneItems = 8;
 
-__device__ inline bool pair_gt(uint64_t ka, int32_t ia, uint64_t kb, int32_t ib) {
-  return ka > kb || (ka == kb && ia > ib);
-}
-
 // the element at position p takes the smaller of (own, partner) if it is the
 // lower position of an ascending pair or the upper one of a descending pair
-__device__ inline void keep_one(uint64_t &k, int32_t &i, uint64_t k2, int32_t i2, int p,
-                                int stride, int size) {
+__device__ inline void keep_one(uint64_t &k, uint64_t k2, int p, int stride, int size) {
   const bool want_min = ((p & stride) == 0) == ((p & size) == 0);
-  const bool take = want_min ? pair_gt(k, i, k2, i2) : pair_gt(k2, i2, k, i);
+  const bool take = want_min ? k > k2 : k2 > k;
   k = take ? k2 : k;
-  i = take ? i2 : i;
 }
 
 // value of lane (lane ^ LM) of the wave.  Lane xors below 16 are DPP moves
@@ -419,36 +419,29 @@ __device__ inline uint32_t lane_xor(uint32_t v) {
 // one exchange phase between lanes (strides 8 .. 256): for these strides the
 // bits tested by the pair direction lie above the thread's own 8 positions
 template <int LM>
-__device__ inline void zone_lane_phase(uint64_t (&key)[kZoneItems], int32_t (&idx)[kZoneItems],
-                                       int base, int stride, int size) {
+__device__ inline void zone_lane_phase(uint64_t (&key)[kZoneItems], int base, int stride,
+                                       int size) {
   const bool want_min = ((base & stride) == 0) == ((base & size) == 0);
 #pragma unroll
   for (int e = 0; e < kZoneItems; ++e) {
     const uint32_t lo = lane_xor<LM>((uint32_t)key[e]);
     const uint32_t hi = lane_xor<LM>((uint32_t)(key[e] >> 32));
     const uint64_t k2 = ((uint64_t)hi << 32) | lo;
-    const int32_t i2 = (int32_t)lane_xor<LM>((uint32_t)idx[e]);
-    const bool take = want_min ? pair_gt(key[e], idx[e], k2, i2) : pair_gt(k2, i2, key[e], idx[e]);
+    const bool take = want_min ? key[e] > k2 : k2 > key[e];
     key[e] = take ? k2 : key[e];
-    idx[e] = take ? i2 : idx[e];
   }
 }
 
 template <int S>
-__device__ inline void zone_reg_phase(uint64_t (&key)[kZoneItems], int32_t (&idx)[kZoneItems],
-                                      int base, int size) {
+__device__ inline void zone_reg_phase(uint64_t (&key)[kZoneItems], int base, int size) {
 #pragma unroll
   for (int e = 0; e < kZoneItems; ++e) {
     if (e & S) continue;
     const bool up = ((base + e) & size) == 0;
-    const bool gt = pair_gt(key[e], idx[e], key[e + S], idx[e + S]);
-    if (gt == up) {
-      const uint64_t tk = key[e];
-      const int32_t ti = idx[e];
+    if ((key[e] > key[e + S]) == up) {
+      const uint64_t t = key[e];
       key[e] = key[e + S];
-      idx[e] = idx[e + S];
-      key[e + S] = tk;
-      idx[e + S] = ti;
+      key[e + S] = t;
     }
   }
 }
@@ -457,6 +450,7 @@ __global__ __launch_bounds__(1024) void k_zone_sort(const int32_t *__restrict__ 
                                                     const double *__restrict__ z, int n_r,
                                                     const DevState *st, int32_t *order) {
   extern __shared__ __align__(16) char smem[];
+  __shared__ unsigned long long s_lo, s_hi;
   const int64_t na = st->n_active;
   const int zk = blockIdx.x;
   const int64_t b0 = (int64_t)zk * na / n_r, b1 = (int64_t)(zk + 1) * na / n_r;
@@ -465,58 +459,102 @@ __global__ __launch_bounds__(1024) void k_zone_sort(const int32_t *__restrict__ 
   const int P = blockDim.x * kZoneItems;
   const int tid = threadIdx.x;
   const int base = tid * kZoneItems;
-  uint64_t key[kZoneItems];
+  uint64_t bits[kZoneItems];
   int32_t idx[kZoneItems];
+  unsigned long long lo = ~0ull, hi = 0ull;
 #pragma unroll
   for (int e = 0; e < kZoneItems; ++e) {
     const int p = base + e;
+    idx[e] = 0x7FFFFFFF;
+    bits[e] = 0;
     if (p < nk) {
-      const int32_t v = by_r[b0 + p];
-      idx[e] = v;
-      key[e] = key_bits(z[v]);
-    } else {
-      idx[e] = 0x7FFFFFFF;
-      key[e] = ~0ull;
+      idx[e] = by_r[b0 + p];
+      bits[e] = key_bits(z[idx[e]]);
+      lo = bits[e] < lo ? bits[e] : lo;
+      hi = bits[e] > hi ? bits[e] : hi;
     }
   }
+  // range of the zone's bit patterns: 32 significant bits after the shift
+  if (tid == 0) {
+    s_lo = ~0ull;
+    s_hi = 0ull;
+  }
+  __syncthreads();
+  atomicMin(&s_lo, lo);
+  atomicMax(&s_hi, hi);
+  __syncthreads();
+  const uint64_t zmin = s_lo, range = s_hi - s_lo;
+  const int shift = (range >> 32) ? 32 - __clzll((long long)range) : 0;
+  uint64_t key[kZoneItems];
+#pragma unroll
+  for (int e = 0; e < kZoneItems; ++e)
+    key[e] = base + e < nk ? (((bits[e] - zmin) >> shift) << 32) | (uint32_t)idx[e] : ~0ull;
   uint64_t *lk = (uint64_t *)smem;
-  int32_t *li = (int32_t *)(lk + P);
   for (int size = 2; size <= P; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       if (stride >= 64 * kZoneItems) {
 #pragma unroll
-        for (int e = 0; e < kZoneItems; ++e) {
-          lk[base + e] = key[e];
-          li[base + e] = idx[e];
-        }
+        for (int e = 0; e < kZoneItems; ++e) lk[base + e] = key[e];
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < kZoneItems; ++e) {
-          const int q = (base + e) ^ stride;
-          keep_one(key[e], idx[e], lk[q], li[q], base + e, stride, size);
-        }
+        for (int e = 0; e < kZoneItems; ++e) keep_one(key[e], lk[(base + e) ^ stride], base + e, stride, size);
         __syncthreads();
       } else if (stride >= kZoneItems) {
         switch (stride / kZoneItems) {
-          case 1: zone_lane_phase<1>(key, idx, base, stride, size); break;
-          case 2: zone_lane_phase<2>(key, idx, base, stride, size); break;
-          case 4: zone_lane_phase<4>(key, idx, base, stride, size); break;
-          case 8: zone_lane_phase<8>(key, idx, base, stride, size); break;
-          case 16: zone_lane_phase<16>(key, idx, base, stride, size); break;
-          default: zone_lane_phase<32>(key, idx, base, stride, size); break;
+          case 1: zone_lane_phase<1>(key, base, stride, size); break;
+          case 2: zone_lane_phase<2>(key, base, stride, size); break;
+          case 4: zone_lane_phase<4>(key, base, stride, size); break;
+          case 8: zone_lane_phase<8>(key, base, stride, size); break;
+          case 16: zone_lane_phase<16>(key, base, stride, size); break;
+          default: zone_lane_phase<32>(key, base, stride, size); break;
         }
       } else if (stride == 4) {
-        zone_reg_phase<4>(key, idx, base, size);
+        zone_reg_phase<4>(key, base, size);
       } else if (stride == 2) {
-        zone_reg_phase<2>(key, idx, base, size);
+        zone_reg_phase<2>(key, base, size);
       } else {
-        zone_reg_phase<1>(key, idx, base, size);
+        zone_reg_phase<1>(key, base, size);
       }
     }
   }
+  if (shift > 0) {
+    // runs of equal reduced keys, re-sorted by (full bits, index) by the
+    // thread that holds the run's first position
+    uint64_t *lz = lk + P;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kZoneItems; ++e) {
+      lk[base + e] = key[e];
+      lz[base + e] = base + e < nk ? key_bits(z[(int32_t)(uint32_t)key[e]]) : ~0ull;
+    }
+    __syncthreads();
+    for (int e = 0; e < kZoneItems; ++e) {
+      const int p = base + e;
+      const uint32_t h = (uint32_t)(lk[p] >> 32);
+      if (p + 1 >= nk || (uint32_t)(lk[p + 1] >> 32) != h) continue;
+      if (p > 0 && (uint32_t)(lk[p - 1] >> 32) == h) continue;
+      int end = p + 2;
+      while (end < nk && (uint32_t)(lk[end] >> 32) == h) ++end;
+      for (int a = p + 1; a < end; ++a) {  // insertion sort of [p, end)
+        const uint64_t kv = lk[a], zv = lz[a];
+        const uint32_t iv = (uint32_t)kv;
+        int b = a - 1;
+        while (b >= p && (lz[b] > zv || (lz[b] == zv && (uint32_t)lk[b] > iv))) {
+          lk[b + 1] = lk[b];
+          lz[b + 1] = lz[b];
+          --b;
+        }
+        lk[b + 1] = kv;
+        lz[b + 1] = zv;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kZoneItems; ++e) key[e] = lk[base + e];
+  }
 #pragma unroll
   for (int e = 0; e < kZoneItems; ++e)
-    if (base + e < nk) order[b0 + base + e] = idx[e];
+    if (base + e < nk) order[b0 + base + e] = (int32_t)(uint32_t)key[e];
 }
 
 // member ranges, edges, volumes and gas primaries of every cell
@@ -599,7 +637,7 @@ hipError_t launch_binning(const Model &P, int n_r, int n_z, const double *r, con
   const int64_t zone_max = (N + n_r - 1) / n_r;  // no zone holds more
   if (zone_max <= kZoneSortMax) {
     const int Pz = zone_sort_size(zone_max);
-    const size_t lds = Pz > 64 * kZoneItems ? (size_t)Pz * (sizeof(uint64_t) + sizeof(int32_t)) : 0;
+    const size_t lds = (size_t)Pz * 2 * sizeof(uint64_t);  // keys, then full bits for the runs
     if (lds > 64 * 1024) {
       e = hipFuncSetAttribute((const void *)k_zone_sort, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);

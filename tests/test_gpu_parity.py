@@ -42,13 +42,15 @@ def test_philox_words_bit_exact():
 # (N, n_r, n_z, seed, ulp_clusters): zones of up to 8192 members are ordered
 # in LDS (16384 / 2 is that maximum), larger ones (40000 / 3, 30000 / 1) take
 # the global radix path (cells stay small enough for the FP64 step);
-# ulp_clusters puts a fifth of the radii within a few ulps of each other so
-# that the 32-bit r keys tie and the exact fix-up runs
+# ulp_clusters "r" puts a fifth of the radii within a few ulps of each other
+# so that the 32-bit r keys tie and the exact fix-up runs; "z" does the same
+# for heights inside zones ordered in LDS, whose 32-bit reduced z keys then
+# tie and are re-sorted by full bits
 @pytest.mark.parametrize("N,n_r,n_z,seed,ulp", [
     (5000, 10, 5, 0, False), (4000, 1, 20, 1, False), (2049, 7, 3, 2, False),
     (100_000, 50, 10, 3, False), (33, 4, 8, 4, False), (16384, 2, 9, 5, False),
-    (40000, 3, 20, 6, False), (30000, 1, 30, 7, True), (20000, 40, 4, 8, True),
-    (1, 1, 1, 9, False)])
+    (40000, 3, 20, 6, False), (30000, 1, 30, 7, "r"), (20000, 40, 4, 8, "r"),
+    (20000, 10, 8, 10, "z"), (16384, 2, 16, 11, "z"), (1, 1, 1, 9, False)])
 def test_binning_bit_exact(N, n_r, n_z, seed, ulp):
     api = _api()
     rng = np.random.default_rng(seed)
@@ -60,12 +62,20 @@ def test_binning_bit_exact(N, n_r, n_z, seed, ulp):
         r[k[: len(k) // 2]] = r[k[len(k) // 2: 2 * (len(k) // 2)]]
         z[k[::3]] = z[k[0]]
         z[k[1::7]] = 0.0
-    if ulp:
+    if ulp == "r":
         # clusters of 40 around a few centres, offsets of 0..60 ulps, some equal
         c = rng.choice(N, N // 5, replace=False)
         centres = W.AU * 10.0 ** rng.uniform(0, 2, len(c) // 40 + 1)
         base = centres[np.arange(len(c)) // 40]
         r[c] = base + rng.integers(0, 60, len(c)) * np.spacing(base)
+    elif ulp == "z":
+        # heights over many binades (so the reduced keys drop low bits), and
+        # clusters of 40 within 0..60 ulps of a few centres, some equal
+        z = W.AU * 10.0 ** rng.uniform(-8, 0, N)
+        c = rng.choice(N, N // 5, replace=False)
+        centres = W.AU * 10.0 ** rng.uniform(-4, -1, len(c) // 40 + 1)
+        base = centres[np.arange(len(c)) // 40]
+        z[c] = base + rng.integers(0, 60, len(c)) * np.spacing(base)
     active = (rng.random(N) > 0.1).astype(np.uint8)
     if N == 1:
         active[:] = 1
