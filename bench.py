@@ -409,9 +409,21 @@ def ensemble_report(work, pick, seeds=8, steps=2):
     return out
 
 
-def cpu_baseline(work, target_s=12.0):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(work, target_s=12.0, one_thread_s=3.0):
     """The FP64 oracle on a bounded sample of cells of the same workload,
-    threads over cells on every host core."""
+    threads over cells on every host core; then the same on one thread over
+    a smaller sample.  Collisions/s and algorithmic pair evaluations/s."""
     import numpy as np
 
     import oracle as O
@@ -419,25 +431,36 @@ def cpu_baseline(work, target_s=12.0):
 
     threads = os.cpu_count() or 1
     rng = np.random.default_rng(7)
-    n_cells = len(work["cells"]["cell_start"]) - 1
-    k = max(threads, 8)
-    used = 0.0
-    evs = 0
-    ncells = 0
+    sizes = np.diff(work["cells"]["cell_start"])
+    n_cells = len(sizes)
     perm = rng.permutation(n_cells)
-    while used < target_s and ncells < n_cells:
-        cells = np.sort(perm[ncells:ncells + k])
-        sub = W.subset_cells(work, cells)
-        part = {kk: (v.copy() if isinstance(v, np.ndarray) else v) for kk, v in sub["particles"].items()}
-        t0 = time.perf_counter()
-        out = O.collide_all(sub["params"], sub["cells"], 0, part, 0.0, EVENTS_PER_CELL, threads=threads)
-        used += time.perf_counter() - t0
-        evs += int(out["stats"]["events"].sum())
-        ncells += len(cells)
-        k = min(2 * k, n_cells - ncells) if used < target_s / 4 else k
+
+    def run(nthreads, budget, k):
+        used, evs, ncells, evals = 0.0, 0, 0, 0.0
+        while used < budget and ncells < n_cells:
+            cells = np.sort(perm[ncells:ncells + k])
+            sub = W.subset_cells(work, cells)
+            part = {kk: (v.copy() if isinstance(v, np.ndarray) else v) for kk, v in sub["particles"].items()}
+            t0 = time.perf_counter()
+            out = O.collide_all(sub["params"], sub["cells"], 0, part, 0.0, EVENTS_PER_CELL,
+                                threads=nthreads)
+            used += time.perf_counter() - t0
+            ev = out["stats"]["events"]
+            evs += int(ev.sum())
+            n = sizes[cells].astype("float64")
+            evals += float((n * (n + 1) / 2).sum() + (ev * n).sum())
+            ncells += len(cells)
+            k = min(2 * k, n_cells - ncells) if used < budget / 4 else k
+        return used, evs, ncells, evals
+
+    used, evs, ncells, evals = run(threads, target_s, max(threads, 8))
+    u1, e1, c1, p1 = run(1, one_thread_s, 2)
     return dict(value=evs / used, unit="collisions/s", cores=threads, kind="oracle",
                 sample=f"{ncells} of {n_cells} cells of the same workload, {EVENTS_PER_CELL} events "
-                       f"each ({evs} events), FP64, {used:.1f} s wall")
+                       f"each ({evs} events), FP64, {used:.1f} s wall",
+                pair_evals_per_s=evals / used, cpu_model=cpu_model(),
+                one_thread={"collisions_per_s": e1 / u1, "pair_evals_per_s": p1 / u1,
+                            "sample": f"{c1} cells, {e1} events, {u1:.1f} s"})
 
 
 def main():
