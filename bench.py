@@ -275,6 +275,80 @@ def next_rows(steps, warmup):
     return res
 
 
+def configs_table(steps=10):
+    """Per-configuration rates of the GPU forms and of the FP64 oracle, on the
+    parity-test configurations (one cell with the constant kernel; one column;
+    the 1e5-particle disk) and the 2e6-particle disk.  GPU: FP64 plain and
+    mixed batched (autotuned), `steps` steps after 2 warm-ups (the single
+    cell: its one step to t = 1998, three fresh runs); oracle: every host core,
+    the first steps of the same run.  Collisions/s = events / wall time of
+    the steps (binning and transport included where the configuration has
+    them)."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_2507_21239_amd import api
+    from paper_2507_21239_amd import workloads as W
+
+    threads = os.cpu_count() or 1
+
+    def fresh(work):
+        return {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in work["particles"].items()}
+
+    def gpu(work, precision, schedule, n):
+        dev = api.to_device(fresh(work))
+        sim = api.Simulation(work["params"], dev, precision=precision, schedule=schedule)
+        sim.bin(api.cells_to_device(work["cells"]) if work["cells"] is not None else None)
+        dt, me = work["dt"], work.get("max_events", 0)
+        if schedule == "batched":
+            choose_schedule(sim, dt, me)
+        if n > 1:
+            sim.step(dt, me, 2)
+        ev0 = sim.stats()["events"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(dt, me, n)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ev = sim.stats()["events"] - ev0
+        sim.close()
+        return wall, ev
+
+    def oracle(work, n):
+        part = fresh(work)
+        t0 = time.perf_counter()
+        ev = 0
+        for s in range(n):
+            out = O.step(work["params"], part, s, work["dt"], work.get("max_events", 0),
+                         cells=work["cells"], threads=threads)
+            ev += int(out["stats"]["events"].sum())
+        return time.perf_counter() - t0, ev
+
+    def row(name, work, g_steps, o_steps, reps=1):
+        r = {"particles": len(work["particles"]["m"])}
+        for precision, schedule in (("fp64", "plain"), ("mixed", "batched")):
+            log("configs:", name, precision, schedule)
+            runs = [gpu(work, precision, schedule, g_steps) for _ in range(reps)]
+            wall, ev = sorted(runs)[len(runs) // 2]
+            r[f"gpu_{precision}_{schedule}"] = {"ms_per_step": wall / g_steps * 1e3,
+                                                "events_per_step": ev / g_steps,
+                                                "collisions_per_s": ev / wall}
+        log("configs:", name, "oracle")
+        runs = [oracle(work, o_steps) for _ in range(reps)]
+        wall, ev = sorted(runs)[len(runs) // 2]
+        r["oracle"] = {"threads": threads, "steps": o_steps, "ms_per_step": wall / o_steps * 1e3,
+                       "events_per_step": ev / o_steps, "collisions_per_s": ev / wall}
+        return r
+
+    res = {}
+    res["single_cell_constant_kernel"] = row("single cell", W.c1_single_cell(seed=0), 1, 1, reps=3)
+    res["column_20x200"] = row("column", W.c2_column(seed=0), steps, 20)
+    res["disk_1e5"] = row("disk 1e5", W.c3_disk(seed=0), steps, 10)
+    res["disk_2e6"] = row("disk 2e6", W.c5_large_disk(seed=0), steps, 1)
+    return res
+
+
 def copy_calibration():
     import torch
     x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -472,7 +546,8 @@ def main():
     ap.add_argument("--no-error", action="store_true", help="skip the error report")
     ap.add_argument("--modes", default="all",
                     help="all | headline | none (only the full step, for profiling) | "
-                         "next (cost of the NEXT rows)")
+                         "next (cost of the NEXT rows) | configs (per-configuration rates, "
+                         "GPU forms and oracle)")
     ap.add_argument("--no-full-step", action="store_true", help="skip the full-path measurement")
     ap.add_argument("--schedule", default=None,
                     help="SMALL_MAX,GRID_PER_CU: fixed batched schedule instead of the autotuner "
@@ -506,6 +581,11 @@ def main():
     if args.modes == "next":
         print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
                           "next_rows": next_rows(args.steps, args.warmup)}), flush=True)
+        return
+    if args.modes == "configs":
+        print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
+                          "cpu_model": cpu_model(), "configs": configs_table(args.steps)}),
+              flush=True)
         return
     if args.modes == "none":
         fs = full_step(args.steps, args.warmup)
