@@ -39,7 +39,7 @@ template <>
 struct RecStore<float> {
   float4 *A;  // im, a, St, h
   float4 *B;  // q1, vr, vp, vz
-  float4 *C;  // nd, m, ist, -
+  float4 *C;  // nd, m, ist, Mn
   __device__ RecStore(char *base, int cap)
       : A((float4 *)base), B((float4 *)base + cap), C((float4 *)base + 2 * cap) {}
   __device__ Rec<float> load(int s) const {
@@ -47,13 +47,13 @@ struct RecStore<float> {
     Rec<float> r;
     r.im = a.x; r.a = a.y; r.St = a.z; r.h = a.w;
     r.q1 = b.x; r.vr = b.y; r.vp = b.z; r.vz = b.w;
-    r.nd = c.x; r.m = c.y; r.ist = c.z;
+    r.nd = c.x; r.m = c.y; r.ist = c.z; r.Mn = c.w;
     return r;
   }
   __device__ void store(int s, const Rec<float> &r) const {
     A[s] = make_float4(r.im, r.a, r.St, r.h);
     B[s] = make_float4(r.q1, r.vr, r.vp, r.vz);
-    C[s] = make_float4(r.nd, r.m, r.ist, 0.0f);
+    C[s] = make_float4(r.nd, r.m, r.ist, r.Mn);
   }
 };
 
@@ -68,6 +68,7 @@ struct RecStore<double> {
     Rec<double> r;
     r.im = a.x; r.a = a.y; r.St = b.x; r.h = b.y; r.q1 = c.x; r.vr = c.y;
     r.vp = d.x; r.vz = d.y; r.nd = e.x; r.m = e.y; r.ist = f.x;
+    r.Mn = 0.0;  // not held: the FP64 state is rebuilt from M
     return r;
   }
   __device__ void store(int s, const Rec<double> &r) const {
@@ -86,7 +87,7 @@ template <typename RT>
 __device__ inline Rec<RT> empty_rec() {
   Rec<RT> r;
   r.m = r.im = r.St = r.ist = (RT)1;
-  r.a = r.h = r.vr = r.vp = r.vz = r.nd = (RT)0;
+  r.a = r.h = r.vr = r.vp = r.vz = r.nd = r.Mn = (RT)0;
   r.q1 = (RT)0.5;
   return r;
 }
@@ -381,14 +382,16 @@ template <typename RT>
 struct RecAfter;
 template <>
 struct RecAfter<double> {
-  __device__ static Rec<double> get(const Model &P, const TeamScratch *S, double m, double M) {
+  __device__ static Rec<double> get(const Model &P, const TeamScratch *S, double m, double M,
+                                    double) {
     return make_rec<double>(P, S->gas, m, M, 1.0);
   }
 };
 template <>
 struct RecAfter<float> {
-  __device__ static Rec<float> get(const Model &, const TeamScratch *S, double m, double M) {
-    return make_rec_f(S->cf, m, M);
+  __device__ static Rec<float> get(const Model &, const TeamScratch *S, double m, double,
+                                   float Mn) {
+    return make_rec_f(S->cf, m, Mn);
   }
 };
 
@@ -514,8 +517,9 @@ __device__ inline Cand team_pick(Team &tm, double incl, double part, const VT *v
   return pick_all_waves<KMAX>(tm, incl, part, v, K, target, a0, a1, ai);
 }
 
-// Outcome of an event for i (mass mi, swarm mass Mi) hitting j's swarm (mass
-// mj) at relative velocity dvj: new mass, outcome code and i's new record.
+// Outcome of an event for i (mass mi, swarm mass Mi; the FP32 form takes the
+// record's Mn instead) hitting j's swarm (mass mj) at relative velocity dvj:
+// new mass, outcome code and i's new record.
 // The writer also applies the side effects: the anomaly flag and the
 // mass-weighted composition of i on sticking or fragmentation (lanes below
 // n_comp, one component each).
@@ -526,8 +530,9 @@ __device__ inline Cand team_pick(Team &tm, double incl, double part, const VT *v
 // in FP32
 template <typename RT, bool PROB>
 __device__ inline int event_outcome(const CollideArgs &A, const TeamScratch *S, double mi,
-                                    double mj, double Mi, RT dvj, double u4, double u5, int gi,
-                                    int gj, int lane, bool writer, double &mnew, Rec<RT> &rin) {
+                                    double mj, double Mi, RT Mn, RT dvj, double u4, double u5,
+                                    int gi, int gj, int lane, bool writer, double &mnew,
+                                    Rec<RT> &rin) {
   const OutcomeConst &P = S->oc;
   bool fast;
   if constexpr (PROB) {
@@ -546,7 +551,7 @@ __device__ inline int event_outcome(const CollideArgs &A, const TeamScratch *S, 
       cs[gi] = (float)((wi * cI + wj * cJ) / (wi + wj));
     }
   }
-  rin = RecAfter<RT>::get(A.P, S, mnew, Mi);
+  rin = RecAfter<RT>::get(A.P, S, mnew, Mi, Mn);
   return oc;
 }
 
@@ -743,7 +748,16 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     }
     const int rl = (int)(e - e0);
     if (timed) {
-      const double tau = readlane_d(nlu1, rl) / Rtot * scale;  // exponential waiting time
+      // exponential waiting time; the FP32 form takes 1/R from the hardware
+      // estimate and one Newton step
+      double tau;
+      if constexpr (sizeof(RT) == 4) {
+        double ir = __builtin_amdgcn_rcp(Rtot);
+        ir = fma(fma(-Rtot, ir, 1.0), ir, ir);
+        tau = readlane_d(nlu1, rl) * ir * scale;
+      } else {
+        tau = readlane_d(nlu1, rl) / Rtot * scale;
+      }
       if (t + tau > A.dt) break;  // the next event falls outside the step
       t += tau;
     }
@@ -759,7 +773,9 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     const int i_local = ci.lane * K + ci.q;
     const double mi = ci.p0, ri_old = ci.p1;
     const int gi = ci.gi;
-    const double Mi = A.M[gi];  // needed after the outcome: the load overlaps row i
+    // the FP64 state of i is rebuilt from its swarm mass (the load overlaps
+    // row i); the FP32 record carries it
+    const double Mi = sizeof(RT) == 8 ? A.M[gi] : 0.0;
     const Rec<RT> ri = R.load(si);
 
     // -- row i before the event: r_ij, r_ji and the relative velocities
@@ -804,7 +820,8 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
                                     m64, dvv, gix);
     double mnew = 0.0;
     Rec<RT> rin;
-    const int oc = event_outcome<RT, PROB>(A, tm.S, mi, cj.p0, Mi, (RT)cj.p1, readlane_d(uu4, rl),
+    const int oc = event_outcome<RT, PROB>(A, tm.S, mi, cj.p0, Mi, ri.Mn, (RT)cj.p1,
+                                           readlane_d(uu4, rl),
                                            PROB ? readlane_d(uu5, rl) : 0.0, gi, cj.gi, lane,
                                            wave == 0, mnew, rin);
     if (tl == 0) log_event(A, cell, e, i_local, cj.lane * K + cj.q, oc);

@@ -233,6 +233,7 @@ struct Rec {
   RT vz;   // settling velocity at the cell height
   RT nd;   // swarm number density M/(m V), times the cell's rate scale
   RT ist;  // 1 / St
+  RT Mn;   // swarm mass M / V times the rate scale (nd = Mn / m)
 };
 
 // the FP32 record carries sqrt(pi) a in place of a, so that the collision
@@ -262,6 +263,7 @@ __host__ __device__ inline Rec<RT> make_rec(const Model &P, const Gas &g, double
   o.vp = (RT)(-g.eta_vK / (1.0 + St * St));
   o.vz = (RT)(-g.z_c * g.Omega * St / (1.0 + St));
   o.nd = (RT)(M / (m * g.V) * nd_scale);
+  o.Mn = (RT)(M * (nd_scale / g.V));
   return o;
 }
 
@@ -321,7 +323,9 @@ __host__ __device__ inline PairConst<RT> make_pair_const(const Model &P, const G
 }
 
 // FP32 particle state of the mixed path (after a collision changed m)
-__device__ inline Rec<float> make_rec_f(const CellF &c, double m, double M) {
+// Mn: the particle's swarm mass times the cell's density factor, as the
+// record holds it ((float)(M * nd_fac))
+__device__ inline Rec<float> make_rec_f(const CellF &c, double m, float Mn) {
   const float mf = (float)m;
   const float a = cbrtf(mf * c.ca);
   const float ts = a < c.a_sw ? c.tE * a : c.tS * a * a;
@@ -339,7 +343,8 @@ __device__ inline Rec<float> make_rec_f(const CellF &c, double m, double M) {
   r.vr = c.m2eta * St * w;
   r.vp = c.meta * w;
   r.vz = c.mzO * St * q1;
-  r.nd = (float)(M * c.nd_fac) * r.im;
+  r.nd = Mn * r.im;
+  r.Mn = Mn;
   return r;
 }
 
