@@ -846,7 +846,11 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
         RT dv, a_iq, a_qi;
         PairEval<RT, FAST>::run(pc, rin, rq, dv, a_iq, a_qi);
         part2 += a_iq;
-        const double x = (r[q] - (double)rji[q]) + (double)a_qi;
+        // FP64: old term out, new term in, as the oracle orders them; FP32:
+        // the change of r_qi in FP32 (one rounding of a difference far
+        // below the row sum), then one FP64 addition
+        const double x = sizeof(RT) == 8 ? (r[q] - (double)rji[q]) + (double)a_qi
+                                         : r[q] + (double)(a_qi - rji[q]);
         const bool upd = s != si && ((valid >> q) & 1u);
         r[q] = upd ? (x > 0.0 ? x : 0.0) : r[q];
       }
