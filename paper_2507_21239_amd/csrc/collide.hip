@@ -321,16 +321,13 @@ struct Team {
   }
   // team-inclusive prefix of x over team lanes; total on every lane.  Teams
   // have one wave or four; the offset and total add the wave totals in wave
-  // order (FP64).  ST: the precision of the in-wave scan (FP64 for the FP64
-  // form; FP32 for the mixed form, whose prefixes only place the targets of
-  // the selections)
-  template <typename ST>
+  // order
   __device__ double scan(double x, double &total) {
-    const ST inc = wave_incl_scan((ST)x);
-    const double wt = (double)readlane_t(inc, 63);
+    const double inc = wave_incl_scan(x);
+    const double wt = readlane_d(inc, 63);
     if (nw == 1) {
       total = wt;
-      return (double)inc;
+      return inc;
     }
     phase ^= 1;
     if (lane == 63) S->tot[phase][wave] = wt;
@@ -344,20 +341,19 @@ struct Team {
       tot += t[w];
     }
     total = tot;
-    return off + (double)inc;
+    return off + inc;
   }
-  // team-inclusive prefix of a plus the totals of a and b (one exchange); a
-  // is scanned over each wave in precision ST, b summed in its own precision
-  // (BT), then both in FP64
-  template <typename ST, typename BT>
+  // team-inclusive prefix of a plus the totals of a and b (one exchange); b
+  // is summed over each wave in its own precision (BT), then in FP64
+  template <typename BT>
   __device__ double scan2(double a, BT b, double &tot_a, double &tot_b) {
-    const ST ia = wave_incl_scan((ST)a);
+    const double ia = wave_incl_scan(a);
     const BT ib = wave_incl_scan(b);
-    const double wa = (double)readlane_t(ia, 63), wb = (double)readlane_t(ib, 63);
+    const double wa = readlane_d(ia, 63), wb = (double)readlane_t(ib, 63);
     if (nw == 1) {
       tot_a = wa;
       tot_b = wb;
-      return (double)ia;
+      return ia;
     }
     phase ^= 1;
     if (lane == 63) {
@@ -377,7 +373,7 @@ struct Team {
     }
     tot_a = ta;
     tot_b = tb;
-    return off + (double)ia;
+    return off + ia;
   }
 };
 
@@ -713,7 +709,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
 #pragma unroll
   for (int q = 0; q < KMAX; ++q)
     if (q < K) part += r[q];
-  double incl = tm.scan<RT>(part, Rtot);
+  double incl = tm.scan(part, Rtot);
   // lanes from team lane 64 fix_wave on carry delta on top of the latest
   // scanned prefix (the new row sum of the previous event's i)
   int fix_wave = nw;
@@ -798,7 +794,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
       part1 += (double)rij[q];
     }
     double Ri;
-    const double incl1 = tm.scan<RT>(part1, Ri);
+    const double incl1 = tm.scan(part1, Ri);
     if (!(Ri > 0.0)) {
       // row i has no partner left (its stored sum was rounding residue):
       // clear it and count a null event
@@ -813,7 +809,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
 #pragma unroll
       for (int q = 0; q < KMAX; ++q)
         if (q < K) part += r[q];
-      incl = tm.scan<RT>(part, Rtot);
+      incl = tm.scan(part, Rtot);
       fix_wave = nw;
       delta = 0.0;
       continue;
@@ -867,7 +863,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     for (int q = 0; q < KMAX; ++q)
       if (q < K) part += r[q];
     double ri_new;
-    incl = tm.scan2<RT>(part, part2, Rtot, ri_new);
+    incl = tm.scan2(part, part2, Rtot, ri_new);
     delta = ri_new - ri_old;
     fix_wave = ci.lane >> 6;
     if (tl >= ci.lane) incl += delta;
