@@ -616,7 +616,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "precision": "FP32 pair rates and in-wave selection prefixes; FP64 masses, row-sum state, wave totals and time",
+        "precision": "FP32 pair rates; FP64 masses, prefix sums, row-sum state and time",
         "data": "synthetic",
         "config": {"workload": "batched collision step: 4096 cells, counts log-uniform [64,1024], "
                                "masses log-uniform 1e-12..1e2 g, random gas, 1000 events/cell",

@@ -68,8 +68,7 @@ typedef enum {
 /* arithmetic of the rate matrix */
 #define MCD_FP64 0  /* rates, sums and masses in FP64 */
 #define MCD_MIXED 1 /* pair rates in FP32 (per-cell power-of-two scale);
-                       masses, row-sum state and time in FP64; in-wave
-                       selection prefixes in FP32 */
+                       masses, prefix sums, row-sum state and time in FP64 */
 
 /* cell schedule of the collision kernel */
 #define MCD_SCHED_PLAIN 0   /* one four-wave workgroup per cell, launched per step */
@@ -203,7 +202,7 @@ mcd_status mcd_step(mcd_ctx *ctx, double dt, int64_t max_events_per_cell, int32_
 /* Schedule of the batched collision launch (one persistent launch over all
  * cells, largest cells first): which team shape processes a cell and how
  * many workgroups run at once.  Results depend on it only through the
- * rounding order of the prefix scans, which follows the team layout. */
+ * rounding order of the FP64 prefix scans, which follows the team layout. */
 typedef struct {
   int32_t small_max;   /* cells of up to small_max particles run on one
                           wavefront, larger ones on teams of four (0..512) */

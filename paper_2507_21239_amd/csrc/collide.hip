@@ -10,9 +10,9 @@
 // particles).  The cell's n particles are in canonical order j = 0..n-1; team
 // lane t owns the contiguous slots j = t*K .. t*K+K-1 (K = ceil(n/(64 nw))),
 // so the cumulative rate of j is the team prefix of the lanes' partial sums
-// plus a short in-lane prefix.  Prefix sums are DPP scans (FP64 in the FP64
-// form, FP32 in the mixed form); four-wave teams exchange FP64 wave totals
-// through LDS (one barrier per scan).  A
+// plus a short in-lane prefix.  Prefix sums are FP64 DPP scans in both
+// forms; four-wave teams exchange wave totals through LDS (one barrier per
+// scan).  A
 // selection is made by the wave whose prefix range holds the target -- every
 // wave finds it from the exchanged totals -- and published with one more
 // barrier.  The uniforms of 64 events are drawn at once, one event per lane.
