@@ -55,6 +55,11 @@ EVENTS_PER_CELL = 1000
 # and compared at run time; on any change `traffic` is reported as null.
 TRAFFIC = {"fetch_kib": 15397.8, "write_kib": 13231.1, "fetch_factor": 1.99991, "write_factor": 1.0,
            "sources_sha256": "de5550258cbcd1bad7a099e65df99fc71ec86b7dad39d8b554b2ac9ec2aad22d"}
+# Issue rate of the same launch from one `rocprofv3 --pmc` pass of SQ counters:
+# VALU busy = 4 * SQ_ACTIVE_INST_VALU / (1024 SIMDs * launch cycles at 2.4 GHz),
+# and SQ_INSTS_VALU per collision; the same validity rule as TRAFFIC.
+ISSUE = {"valu_busy": 0.821, "valu_insts_per_collision": 1701,
+         "sources_sha256": "de5550258cbcd1bad7a099e65df99fc71ec86b7dad39d8b554b2ac9ec2aad22d"}
 KERNEL_SOURCES = ("paper_2507_21239_amd/csrc/collide.hip", "paper_2507_21239_amd/csrc/physics.hpp",
                   "paper_2507_21239_amd/csrc/device_common.hpp", "paper_2507_21239_amd/csrc/internal.hpp")
 
@@ -74,6 +79,14 @@ def traffic_bytes():
     if t["fetch_kib"] is None or t["sources_sha256"] != kernel_sources_sha256():
         return None
     return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
+
+
+def issue_rate():
+    """Counter-derived VALU busy fraction and instructions per collision, or
+    (None, None) if the kernel changed."""
+    if ISSUE["sources_sha256"] != kernel_sources_sha256():
+        return None, None
+    return ISSUE["valu_busy"], ISSUE["valu_insts_per_collision"]
 
 
 def log(*a):
@@ -629,7 +642,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_bytes(),
                      "kernel": "collide_batched<float>", "flops_per_pair": F_PAIR,
-                     "pair_evals_per_launch": evals},
+                     "pair_evals_per_launch": evals, "valu_busy": issue_rate()[0],
+                     "valu_insts_per_collision": issue_rate()[1]},
     }
     if "fp64_plain" in res:
         out["speedup_mixed_batched_vs_fp64_plain"] = head["collisions_per_s"] / res["fp64_plain"]["collisions_per_s"]
