@@ -5,6 +5,7 @@ sigma_d(m, r), the dust surface density per particle-mass bin and radius.
 
     python -m paper_2507_21239_amd.disk_run --particles 100000 --nr 50 --nz 10 \\
         --years 10000 --out sigma.npz
+    python -m paper_2507_21239_amd.disk_run --compare a.npz b.npz
 
 Synthetic initial state (monomers, log-spaced start radii, Sigma_d ~ r^-1,
 half-normal heights), all steps on the GPU; the output file holds sigma
@@ -92,7 +93,45 @@ def run(N: int = 100_000, n_r: int = 50, n_z: int = 10, years: float = 1e4, dt_y
     return out
 
 
+def compare(a: dict, b: dict) -> dict:
+    """Differences between two sigma_d(m, r) results on the same edges: the
+    largest gap between their cumulative mass fractions over mass bins
+    (summed over radius), the difference of the mass-weighted mean log10 m,
+    the relative difference of the total, and the median and largest gap
+    between their radial profiles of the mass-weighted mean log10 m."""
+    if not (np.array_equal(a["m_edges"], b["m_edges"]) and a["sigma"].shape == b["sigma"].shape):
+        raise ValueError("sigma_d results on different bins")
+    lm = 0.5 * (np.log10(a["m_edges"][1:]) + np.log10(a["m_edges"][:-1]))
+
+    def moments(s):
+        w = s.sum(axis=0)
+        return np.cumsum(w) / w.sum(), (w * lm).sum() / w.sum()
+
+    def profile(s):
+        tot = s.sum(axis=1)
+        return np.where(tot > 0, (s * lm).sum(axis=1) / np.where(tot > 0, tot, 1.0), np.nan)
+
+    ca, ma = moments(a["sigma"])
+    cb, mb = moments(b["sigma"])
+    pa, pb = profile(a["sigma"]), profile(b["sigma"])
+    ok = np.isfinite(pa) & np.isfinite(pb)
+    gap = np.abs(pa - pb)[ok]
+    return dict(max_cdf_gap=float(np.max(np.abs(ca - cb))), mean_log_m_diff=float(ma - mb),
+                total_rel_diff=float(a["sigma"].sum() / b["sigma"].sum() - 1.0),
+                profile_median_gap=float(np.median(gap)) if gap.size else float("nan"),
+                profile_max_gap=float(np.max(gap)) if gap.size else float("nan"))
+
+
 def main(argv=None):
+    if argv is None:
+        argv = sys.argv[1:]
+    if argv and argv[0] == "--compare":
+        if len(argv) != 3:
+            raise SystemExit("usage: disk_run --compare A.npz B.npz")
+        a, b = (dict(np.load(f)) for f in argv[1:])
+        for k, v in compare(a, b).items():
+            print(f"{k} {v:.4g}")
+        return
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--particles", type=int, default=100_000)
     ap.add_argument("--nr", type=int, default=50)
