@@ -710,6 +710,19 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
   for (int q = 0; q < KMAX; ++q)
     if (q < K) part += r[q];
   double incl = tm.scan(part, Rtot);
+  // time-limited steps: a cell whose expected event count R dt is large is a
+  // long serial chain that can outlast every other cell of the step, so its
+  // waves get a higher issue priority on their SIMD (the rest fill in around
+  // them); back to the default when the cell is done
+  if (timed) {
+    const double expect = Rtot / scale * A.dt;
+    if (expect >= 256.0)
+      __builtin_amdgcn_s_setprio(3);
+    else if (expect >= 64.0)
+      __builtin_amdgcn_s_setprio(2);
+    else if (expect >= 16.0)
+      __builtin_amdgcn_s_setprio(1);
+  }
   // lanes from team lane 64 fix_wave on carry delta on top of the latest
   // scanned prefix (the new row sum of the previous event's i)
   int fix_wave = nw;
@@ -888,6 +901,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     for (int k = 0; k < 4; ++k)
       if (oc_count[k]) atomicAdd(&A.state->outcomes[k], (unsigned long long)oc_count[k]);
   }
+  __builtin_amdgcn_s_setprio(0);
   tm.sync();  // the region is reused by the next cell
 }
 
