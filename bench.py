@@ -53,13 +53,13 @@ EVENTS_PER_CELL = 1000
 # of WRITE_SIZE: factors 2.0 and 1.0).
 # Valid only for the kernel sources it was taken on: their SHA-256 is kept
 # and compared at run time; on any change `traffic` is reported as null.
-TRAFFIC = {"fetch_kib": 15397.8, "write_kib": 13231.1, "fetch_factor": 1.99991, "write_factor": 1.0,
-           "sources_sha256": "de5550258cbcd1bad7a099e65df99fc71ec86b7dad39d8b554b2ac9ec2aad22d"}
+TRAFFIC = {"fetch_kib": 15117.9, "write_kib": 13231.9, "fetch_factor": 1.99991, "write_factor": 1.0,
+           "sources_sha256": "62e9db6b21be12831df836defd16ad1817b31e75cece44dc22cd7f54c1e9520f"}
 # Issue rate of the same launch from one `rocprofv3 --pmc` pass of SQ counters:
 # VALU busy = 4 * SQ_ACTIVE_INST_VALU / (1024 SIMDs * launch cycles at 2.4 GHz),
 # and SQ_INSTS_VALU per collision; the same validity rule as TRAFFIC.
-ISSUE = {"valu_busy": 0.821, "valu_insts_per_collision": 1701,
-         "sources_sha256": "de5550258cbcd1bad7a099e65df99fc71ec86b7dad39d8b554b2ac9ec2aad22d"}
+ISSUE = {"valu_busy": 0.809, "valu_insts_per_collision": 1672,
+         "sources_sha256": "62e9db6b21be12831df836defd16ad1817b31e75cece44dc22cd7f54c1e9520f"}
 KERNEL_SOURCES = ("paper_2507_21239_amd/csrc/collide.hip", "paper_2507_21239_amd/csrc/physics.hpp",
                   "paper_2507_21239_amd/csrc/device_common.hpp", "paper_2507_21239_amd/csrc/internal.hpp")
 
