@@ -168,11 +168,16 @@ def test_constant_kernel_exact_on_gpu():
 
 
 def test_time_limited_cells_fp64():
+    """Time-limited cells, bit-exact event sequences; their expected event
+    counts span every issue-priority tier of the event loop (below 16 to
+    above 256 events), which must leave the results unchanged."""
     work = W.c4_batched(seed=11, n_cells=24, n_lo=16, n_hi=400, events=0)
     work["dt"] = 1.0e8      # seconds: a few to ~1000 events per cell
     work["max_events"] = 0
     opart, oout = run_oracle_explicit(work, log_per_cell=4096, threads=8)
     assert oout["stats"]["events"].sum() > 1000
+    ev = oout["stats"]["events"]
+    assert ev.min() < 16 and ev.max() >= 256       # every priority tier is reached
     gpart, gstats, glog = run_gpu_explicit(work, "fp64", "batched", log_per_cell=4096)
     assert compare_logs(oout["log"], oout["stats"], glog) == []
     rel = np.abs(gpart["m"] - opart["m"]) / opart["m"]
