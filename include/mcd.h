@@ -238,7 +238,7 @@ mcd_status mcd_set_schedule(mcd_ctx *ctx, int32_t small_max, int32_t grid_per_cu
  * boundary nodes outside; c_s from T, Omega from the star, H = c_s / Omega;
  * eta v_K = c_s^2 s / (2 Omega r) with s = -d ln(rho_g T) / d ln r of the
  * interpolant at (r, z); radial diffusion drifts by D c / r with
- * c = d ln(Sigma_g alpha T) / d ln r + 3/2, Sigma_g(r_k) = 2 (z_0 rho(z_0) +
+ * c = d ln(Sigma_g alpha T) / d ln r + 5/2, Sigma_g(r_k) = 2 (z_0 rho(z_0) +
  * trapezoids over the nodes).  Binning (cell gas), the rate matrix (eta v_K
  * of explicit and adaptive cells) and transport use it from the next call
  * on.  r_nodes == NULL restores the power-law disk.  Synchronises; MCD_EINVAL

@@ -137,7 +137,8 @@ void orc_local_gas_at(const orc_params *P, double r, double z, orc_local_gas *o)
     orc_disk_local(P, r, z, &Sg, &o->T, &o->cs, &o->Omega, &o->H, &o->rho_g);
     o->alpha = P->alpha;
     o->slopeP = P->p + (P->q + 3.0) / 2.0;
-    o->corr = 1.5 - P->q - P->p;
+    /* d ln(r Sigma_g D) / d ln r with Sigma_g ~ r^-p and D ~ c_s H ~ r^(3/2 - q) */
+    o->corr = 2.5 - P->q - P->p;
     return;
   }
   /* bilinear in (ln r, z) of ln rho_g, ln T, ln alpha; r-slopes of the same
@@ -164,7 +165,8 @@ void orc_local_gas_at(const orc_params *P, double r, double z, orc_local_gas *o)
   o->H = o->cs / o->Omega;
   o->slopeP = -(slope[0] + slope[1]); /* pressure rho_g c_s^2 ~ rho_g T */
   const double dlnS = (G->lS[k + 1] - G->lS[k]) / dx;
-  o->corr = dlnS + slope[2] + slope[1] + 1.5;
+  /* d ln(r Sigma_g D) / d ln r, D ~ alpha c_s H ~ alpha T r^(3/2) */
+  o->corr = dlnS + slope[2] + slope[1] + 2.5;
 }
 
 /* derived gas state of a cell from its six primaries (V, rho_g, T, alpha,
@@ -609,8 +611,15 @@ void orc_collide_all(const orc_params *P, int32_t n_cells, const int32_t *cell_s
 /* Transport (paper, Summary: radial and vertical).  A random walk with       */
 /* uniform kicks of variance 2 D dt (Ciesla 2010 type), D = alpha cs H /     */
 /* (1 + St^2); semi-implicit settling toward the midplane with the gas-      */
-/* density correction D/H^2; radial drift plus the Sigma-gradient correction */
-/* D (3/2 - q - p)/r; mirror symmetry folds z; r < r_in leaves the grid.     */
+/* density correction D/H^2; mirror symmetry folds z; r < r_in leaves the    */
+/* grid.  Radially the walk drifts by (D/r) d ln(r Sigma_g D)/d ln r on top  */
+/* of the gas-drag drift: the probability density of a particle's radius,   */
+/* per unit r, is P = 2 pi r Sigma_d, and a tracer's concentration          */
+/* Sigma_d/Sigma_g diffuses through rings of circumference 2 pi r, so        */
+/* dP/dt = d/dr [D w d(P/w)/dr] with w = r Sigma_g; the Ito walk with kicks  */
+/* of variance 2 D dt has this Fokker-Planck equation when its drift is      */
+/* D/w dw/dr + dD/dr.  For the power-law disk the factor is 5/2 - p - q.    */
+/* The particle's 1/(1 + St^2) is held fixed over the derivative.            */
 /* ------------------------------------------------------------------------ */
 void orc_transport(const orc_params *P, int64_t N, double *r, double *z, const double *m,
                    uint8_t *active, uint32_t step, double dt) {

@@ -108,7 +108,8 @@ __host__ __device__ inline DiskPoint disk_at(const Model &P, double r, double z)
 // frequency, scale height, pressure slope s = -d ln P / d ln r (eta v_K =
 // c_s^2 s / (2 Omega r)) and the radial-diffusion correction factor c (the
 // random walk drifts by D c / r: the logarithmic r-derivative of
-// Sigma_g alpha c_s H)
+// r Sigma_g D with D ~ alpha c_s H, the drift under which an axisymmetric
+// random walk keeps a tracer distributed like the gas)
 struct LocalGas {
   double rho_g, T, alpha, cs, Omega, H, slopeP, corr;
 };
@@ -154,7 +155,7 @@ __host__ __device__ inline LocalGas local_gas_at(const Model &P, double r, doubl
     o.H = d.H;
     o.alpha = P.alpha;
     o.slopeP = P.p + (P.q + 3.0) / 2.0;
-    o.corr = 1.5 - P.q - P.p;
+    o.corr = 2.5 - P.q - P.p;  // Sigma_g ~ r^-p, c_s H ~ r^(3/2 - q), times r
     return o;
   }
   int k, l;
@@ -179,7 +180,7 @@ __host__ __device__ inline LocalGas local_gas_at(const Model &P, double r, doubl
   o.H = o.cs / o.Omega;
   o.slopeP = -(slope[0] + slope[1]);  // pressure rho_g c_s^2 ~ rho_g T
   const double dlnS = (G.lS[k + 1] - G.lS[k]) / dx;
-  o.corr = dlnS + slope[2] + slope[1] + 1.5;
+  o.corr = dlnS + slope[2] + slope[1] + 2.5;  // alpha T r^(3/2), times r
   return o;
 }
 

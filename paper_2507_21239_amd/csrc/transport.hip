@@ -5,8 +5,10 @@
 // number, turbulent diffusivity D = alpha c_s H / (1 + St^2); a random walk
 // with uniform kicks of variance 2 D dt; settling toward the midplane and
 // the gas-density correction D/H^2 taken semi-implicitly; radial drift plus
-// the Sigma-gradient correction D (3/2 - q - p)/r; |z| folded by mirror
-// symmetry; particles inside r_in leave the grid.  One thread per particle,
+// the diffusion drift (D/r) d ln(r Sigma_g D)/d ln r (5/2 - q - p for the
+// power-law disk), under which the axisymmetric walk keeps tracers
+// distributed like the gas; |z| folded by mirror symmetry; particles inside
+// r_in leave the grid.  One thread per particle,
 // coalesced FP64 loads and stores.
 #include "device_common.hpp"
 #include "internal.hpp"

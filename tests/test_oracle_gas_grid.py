@@ -42,13 +42,13 @@ def test_nodes_and_midplane_power_laws_are_reproduced():
         # -d ln P / d ln r of the power-law disk at the midplane
         assert a["slopeP"] == pytest.approx(P["p"] + (P["q"] + 3.0) / 2.0, rel=1e-10)
         assert pl["slopeP"] == P["p"] + (P["q"] + 3.0) / 2.0
-        assert pl["corr"] == 1.5 - P["q"] - P["p"]
+        assert pl["corr"] == 2.5 - P["q"] - P["p"]
 
 
 def test_vertical_slab_diffusion_correction_is_exact():
     # rho_g = 1e-9 (r/AU)^-2 up to z = 0.2 AU, T = 300 (r/AU)^-0.6, alpha =
     # 1e-3 (r/AU)^0.5: Sigma_g = 2 z_max rho_g exactly, so the correction
-    # factor is d ln(rho alpha T) / d ln r + 3/2 = -2 + 0.5 - 0.6 + 1.5
+    # factor d ln(r Sigma_g alpha c_s H) / d ln r is -2 + 0.5 - 0.6 + 5/2
     P = W.benchmark_params()
     rn = AU * np.geomspace(1.0, 50.0, 12)
     zn = np.linspace(0.0, 0.2 * AU, 5)
@@ -60,7 +60,7 @@ def test_vertical_slab_diffusion_correction_is_exact():
     for r in AU * np.geomspace(1.3, 45.0, 9):
         for z in (0.0, 0.05 * AU, 0.2 * AU, 1.0 * AU):
             a = O.local_gas(G, r, z)
-            assert a["corr"] == pytest.approx(-2.0 + 0.5 - 0.6 + 1.5, abs=1e-12)
+            assert a["corr"] == pytest.approx(-2.0 + 0.5 - 0.6 + 2.5, abs=1e-12)
             assert a["slopeP"] == pytest.approx(2.0 + 0.6, abs=1e-12)
             assert a["rho_g"] == pytest.approx(1e-9 * (r / AU) ** -2.0, rel=1e-12)
             assert a["alpha"] == pytest.approx(1e-3 * (r / AU) ** 0.5, rel=1e-12)

@@ -2,7 +2,9 @@
 vertical and radial directions) against closed forms: the stationary
 vertical profile of the settling-mixing Fokker-Planck equation, the
 well-mixed limit of tracers, the radial drift speed, the diffusive spread
-of a ring, and removal at the inner edge."""
+of a ring, the planar diffusion law of a radial walk in a uniform gas
+(power-law and gridded), tracers that stay distributed like the gas, and
+removal at the inner edge."""
 import numpy as np
 from scipy import integrate
 
@@ -81,8 +83,7 @@ def test_radial_drift_speed():
 
 def test_radial_spread_of_a_ring():
     # tracers, radial mixing only: variance grows by 2 D dt per step with
-    # D = alpha c_s H; the Sigma-gradient drift D (3/2 - q - p)/r vanishes for
-    # p = 1, q = 0.5.  c_s(10 AU) = 993.6 m/s 10^-1/4, H(10 AU) = 0.0334 AU 10^1.25
+    # D = alpha c_s H; c_s(10 AU) = 993.6 m/s 10^-1/4, H(10 AU) = 0.0334 AU 10^1.25
     p = W.benchmark_params(flags=["tr_mix_r"])
     N, steps = 20000, 50
     r0 = 10 * AU
@@ -94,7 +95,78 @@ def test_radial_spread_of_a_ring():
     D = 1e-3 * 99360.0 * 10 ** -0.25 * 0.0334 * AU * 10 ** 1.25
     var = np.var(part["r"])
     assert abs(var / (2 * D * steps * YR) - 1.0) < 0.04
-    assert abs(np.mean(part["r"]) - r0) < 4 * np.sqrt(var / N)
+
+
+def _tracers(p, r, seed=0):
+    m = 4.0 / 3.0 * np.pi * p["rho_s"] * p["a_mono"] ** 3
+    N = len(r)
+    return dict(r=np.array(r, dtype=np.float64), z=np.zeros(N), m=np.full(N, m), M=np.ones(N),
+                active=np.ones(N, dtype=np.uint8))
+
+
+def _planar_diffusion(p, steps=100, N=400_000, r0=2 * AU):
+    """Mean growth of r^2 of tracers released at r0 and the diffusivity D
+    (constant in r for the disks used here)."""
+    part = _tracers(p, np.full(N, r0))
+    for s in range(steps):
+        O.transport(p, part, s, YR)
+    assert part["active"].all()
+    g = O.local_gas(p, r0, 0.0)
+    D = g["alpha"] * g["cs"] * g["H"]
+    x = part["r"] ** 2 - r0 ** 2
+    return x.mean(), x.std() / np.sqrt(N), 4.0 * D * steps * YR
+
+
+def test_radial_walk_follows_the_planar_diffusion_law():
+    # Sigma_g and D independent of r (p = 0, q = 3/2: c_s H ~ r^(3/2 - q)):
+    # tracers in a uniform gas diffuse like a planar random walk, for which
+    # E[r^2] - r0^2 = E[x^2 + y^2] - r0^2 = 4 D t exactly; a walk with no
+    # geometric drift would give 2 D t, one with the opposite sign 0
+    p = W.benchmark_params(p=0.0, q=1.5, alpha=0.1, r_in=0.0, flags=["tr_mix_r"])
+    got, se, want = _planar_diffusion(p)
+    assert abs(got - want) < 4.0 * se, (got / want, se / want)
+    assert abs(got / want - 1.0) < 0.03, got / want
+
+
+def test_gridded_gas_walk_follows_the_planar_diffusion_law():
+    # the same law through the gridded gas: a slab of constant density and
+    # turbulence with T ~ r^-3/2 (so alpha c_s H is constant), sampled on nodes
+    p = W.benchmark_params(p=0.0, q=1.5, alpha=0.1, r_in=0.0, flags=["tr_mix_r"])
+    rn = AU * np.geomspace(0.05, 20.0, 30)
+    zn = np.linspace(0.0, 0.5 * AU, 4)
+    ones = np.ones(len(zn))
+    grid = dict(r_nodes=rn, z_nodes=zn, rho=np.full((len(rn), len(zn)), 1e-9),
+                T=np.outer(280.0 * (rn / AU) ** -1.5, ones), alpha=np.full((len(rn), len(zn)), 0.1))
+    got, se, want = _planar_diffusion(dict(p, gas_grid=grid))
+    assert abs(got - want) < 4.0 * se, (got / want, se / want)
+    assert abs(got / want - 1.0) < 0.03, got / want
+
+
+def test_tracers_distributed_like_the_gas_stay_so_radially():
+    # a passive tracer whose surface density is proportional to the gas's
+    # stays so: per unit r the particles are distributed ~ r Sigma_g.  Here
+    # Sigma_g ~ r^-1/2 and D ~ r (p = q = 1/2); particles start ~ r^1/2 on
+    # [0.2, 12] AU and the count inside [1, 3] AU, far from both edges, must
+    # not change beyond its sampling noise (at most the square root of the
+    # number of particles that entered or left).  Dropping the walk's
+    # geometric drift moves the count by ~5 % (12 times that noise)
+    p = W.benchmark_params(p=0.5, q=0.5, alpha=0.3, r_in=0.0, flags=["tr_mix_r"])
+    N, steps = 400_000, 100
+    a, b = 0.2, 12.0
+    u = np.random.default_rng(5).random(N)
+    r = AU * (a ** 1.5 + u * (b ** 1.5 - a ** 1.5)) ** (2.0 / 3.0)   # density ~ r^1/2
+    part = _tracers(p, r)
+    inside = lambda x: (x > AU) & (x < 3 * AU)
+    i0 = inside(part["r"])
+    for s in range(steps):
+        O.transport(p, part, s, YR)
+    i1 = inside(part["r"])
+    n0, n1 = int(i0.sum()), int(i1.sum())
+    moved = np.count_nonzero(i0 != i1)
+    expect = N * (3 ** 1.5 - 1) / (b ** 1.5 - a ** 1.5)
+    assert abs(n0 - expect) < 4 * np.sqrt(expect)
+    assert moved > 0.1 * n0                     # the walk did mix across the window's edges
+    assert abs(n1 - n0) < 4 * np.sqrt(moved), (n0, n1, moved)
 
 
 def test_inner_edge_removes_particles():
