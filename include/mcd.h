@@ -189,6 +189,16 @@ mcd_status mcd_bin(mcd_ctx *ctx, const mcd_cells *explicit_or_null);
  * MCD_EINVAL if cell is out of range. */
 mcd_status mcd_rates(mcd_ctx *ctx, int32_t cell, double *r_out, int64_t ld, double *rowsum_out);
 
+/* Starting row sums r_i = sum_j r_ij of every cell (the Zsom & Dullemond
+ * rate of representative particle i, paper Summary), exactly as the
+ * collision launch of the context's precision and schedule builds them
+ * before its first event -- in the mixed form the FP32 build that adds each
+ * unordered pair once -- divided by the cell's rate scale.  out [n of the
+ * grid's members] is a device FP64 array indexed like the grid's order
+ * (out[cell_start[c] + k] belongs to member k of cell c).  No event runs and
+ * no particle changes.  Async; test path.  MCD_ESTATE before mcd_bin. */
+mcd_status mcd_row_sums(mcd_ctx *ctx, double *out);
+
 /* Advance n_steps global steps of length dt [s]: (re)bin when the grid is
  * adaptive, collide every cell, transport.  Inside a cell, events run until
  * the next waiting time would pass dt (dt > 0) and/or max_events_per_cell

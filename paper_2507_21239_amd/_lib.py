@@ -26,7 +26,7 @@ GAS_FIELDS = 6
 GEOM_FIELDS = 5
 
 # every function declared in include/mcd.h
-EXPORTS = ("mcd_init", "mcd_bin", "mcd_rates", "mcd_step", "mcd_tune", "mcd_set_schedule",
+EXPORTS = ("mcd_init", "mcd_bin", "mcd_rates", "mcd_row_sums", "mcd_step", "mcd_tune", "mcd_set_schedule",
            "mcd_set_gas_grid", "mcd_sigma_hist", "mcd_snapshot_bytes", "mcd_snapshot", "mcd_snapshot_wait",
            "mcd_get_stats", "mcd_get_cells", "mcd_set_event_log", "mcd_philox", "mcd_last_error",
            "mcd_free")
@@ -84,6 +84,7 @@ def load() -> C.CDLL:
         "mcd_init": (i32, [C.POINTER(Params), C.POINTER(Particles), vp, C.POINTER(vp)]),
         "mcd_bin": (i32, [vp, C.POINTER(Cells)]),
         "mcd_rates": (i32, [vp, i32, vp, i64, vp]),
+        "mcd_row_sums": (i32, [vp, vp]),
         "mcd_step": (i32, [vp, C.c_double, i64, i32]),
         "mcd_tune": (i32, [vp, C.c_double, i64, C.POINTER(TuneResult)]),
         "mcd_set_schedule": (i32, [vp, i32, i32]),

@@ -144,6 +144,14 @@ class Simulation:
                                        rs.data_ptr()), "mcd_rates")
         return out[:n, :n], rs[:n]
 
+    def row_sums(self, n_members: int) -> torch.Tensor:
+        """Starting row sums of every cell as the collision launch builds
+        them (indexed like the grid's order)."""
+        out = torch.full((max(n_members, 1),), float("nan"), dtype=torch.float64,
+                         device=self.t["m"].device)
+        self._check(self.lib.mcd_row_sums(self.ctx, out.data_ptr()), "mcd_row_sums")
+        return out[:n_members]
+
     def stats(self, check: bool = True) -> dict:
         s = _lib.Stats()
         st = self.lib.mcd_get_stats(self.ctx, C.byref(s))

@@ -289,6 +289,7 @@ CollideArgs collide_args(mcd_ctx *c, double dt, int64_t max_events) {
   a.state = c->d_state;
   a.evlog = c->evlog;
   a.log_per_cell = c->log_per_cell;
+  a.rowsum_dump = nullptr;
   return a;
 }
 
@@ -446,6 +447,18 @@ mcd_status mcd_rates(mcd_ctx *c, int32_t cell, double *r_out, int64_t ld, double
                                    rowsum_out, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "rates");
   MCD_HIP(c, hipStreamSynchronize(c->stream));
+  return MCD_OK;
+}
+
+mcd_status mcd_row_sums(mcd_ctx *c, double *out) {
+  if (!c || !out) return MCD_EINVAL;
+  if (!c->have_cells) return fail(c, MCD_ESTATE, "mcd_row_sums before mcd_bin");
+  CollideArgs a = collide_args(c, 0.0, 1);
+  a.evlog = nullptr;
+  a.rowsum_dump = out;
+  hipError_t e = launch_collide(a, c->prm.precision, c->prm.schedule, c->n_cells, c->max_cell,
+                                c->grid_per_cu * c->cus, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "row sums");
   return MCD_OK;
 }
 

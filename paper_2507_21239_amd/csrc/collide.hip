@@ -698,6 +698,16 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     }
   }
 
+  if (A.rowsum_dump != nullptr) {
+    // test path: the starting row sums as built above, unscaled, at the
+    // members' positions in the cell order; no events
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q)
+      if (q < K && tl * K + q < n) A.rowsum_dump[s0 + tl * K + q] = r[q] / scale;
+    tm.sync();
+    return;
+  }
+
   // ---- events ------------------------------------------------------------
   double t = 0.0;
   uint32_t e = 0;  // events so far (fewer than 2^32 per cell and step)
@@ -740,8 +750,23 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     tm.lane = opaque_v(lane_cell);
     tm.wave = opaque_s(wave_cell);
     if (!(Rtot > 0.0) || !isfinite(Rtot)) {
-      if (!isfinite(Rtot) && tl == 0) atomicOr(&A.state->flags, FLAG_BAD_RATE);
-      break;
+      if (!isfinite(Rtot)) {
+        if (tl == 0) atomicOr(&A.state->flags, FLAG_BAD_RATE);
+        break;
+      }
+      // the running total (the last scan plus the change of r_i) can round
+      // to zero while a row sum still holds a positive remainder: the cell
+      // is done only when a fresh sum of the row sums is zero, as in the
+      // method's definition of R
+      if (fix_wave == nw) break;
+      part = 0.0;
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q)
+        if (q < K) part += r[q];
+      incl = tm.scan(part, Rtot);
+      fix_wave = nw;
+      delta = 0.0;
+      if (!(Rtot > 0.0)) break;
     }
     if (e >= emax) break;
     if (e - e0 >= 64) {
@@ -761,6 +786,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
       }
     }
     const int rl = (int)(e - e0);
+    double t_next = t;
     if (timed) {
       // exponential waiting time; the FP32 form takes 1/R from the hardware
       // estimate and one Newton step
@@ -773,16 +799,31 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
         tau = readlane_d(nlu1, rl) / Rtot * scale;
       }
       if (t + tau > A.dt) break;  // the next event falls outside the step
-      t += tau;
+      t_next = t + tau;
     }
 
     // -- choose i by cumulative row sums (payloads: m_i, old r_i, index)
     const Cand ci = team_pick<KMAX>(tm, incl, part, r, K, readlane_d(uu2, rl) * Rtot, fix_wave,
                                     delta, m64, r, gix);
     if (ci.q < 0) {
+      // no row sum is positive in the running prefixes: decide on a fresh
+      // sum (a total of rounding remainders ends the cell; a positive fresh
+      // total retries the event on the fresh prefixes)
+      if (fix_wave != nw) {
+        part = 0.0;
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q)
+          if (q < K) part += r[q];
+        incl = tm.scan(part, Rtot);
+        fix_wave = nw;
+        delta = 0.0;
+        if (!(Rtot > 0.0)) break;
+        continue;
+      }
       if (tl == 0) atomicOr(&A.state->flags, FLAG_BAD_RATE);
       break;
     }
+    t = t_next;
     const int si = ci.q * TL + ci.lane;
     const int i_local = ci.lane * K + ci.q;
     const double mi = ci.p0, ri_old = ci.p1;

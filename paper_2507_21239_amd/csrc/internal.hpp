@@ -46,6 +46,7 @@ struct CollideArgs {
   DevState *state;
   int32_t *evlog;
   int64_t log_per_cell;
+  double *rowsum_dump;  // test path: starting row sums written here, no events
 };
 
 // a selection result: payloads of the chosen slot, its slot and team lane

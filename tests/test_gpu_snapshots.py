@@ -62,3 +62,29 @@ def test_snapshot_subsets_and_errors():
     assert sim.lib.mcd_snapshot(sim.ctx, 0, 1, 8, None) != 0          # no fields
     assert sim.lib.mcd_snapshot(sim.ctx, 1 << 6, 1, 8, None) != 0     # unknown field
     sim.close()
+
+
+def test_fp64_snapshots_match_the_oracle_state():
+    """Histories against the oracle: FP64 snapshots after every pair of
+    graph-replayed steps of a small disk equal the oracle's state after the
+    same steps (positions and masses within 1e-11, active flags exact,
+    composition within 1e-6)."""
+    import oracle as O
+    sim, dev = _sim("fp64")
+    work = W.c3_disk(seed=11, N=20_000, n_r=20, n_z=5, n_comp=8)
+    ref = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in work["particles"].items()}
+    dt = 5.0 * W.YR
+    snaps = []
+    for k in range(3):
+        say("fp64 snapshot after graph steps", 2 * k + 2)
+        sim.step(dt, 0, 2)
+        snaps.append(sim.snapshot())
+    for k, s in enumerate(snaps):
+        for st in (2 * k, 2 * k + 1):
+            O.step(work["params"], ref, st, dt, 0, threads=8)
+        got = s.wait()
+        assert np.array_equal(got["active"], ref["active"]), k
+        for f in ("r", "z", "m"):
+            assert np.all(np.abs(got[f] - ref[f]) <= 1e-11 * np.abs(ref[f]) + 1e-300), (k, f)
+        assert np.max(np.abs(got["comp"] - ref["comp"])) <= 1e-6, k
+    sim.close()
