@@ -112,11 +112,13 @@ def run_mode(work, precision, schedule, steps, warmup):
     """Plain: one workgroup per cell, each step launched by itself, no
     tuning.  Batched: persistent launch, autotuned schedule, the K timed steps
     replayed from a captured HIP graph (captured during the warm-up)."""
+    import numpy as np
     import torch
     from paper_2507_21239_amd import api
     dev = api.to_device(work["particles"])
     sim = api.Simulation(work["params"], dev, precision=precision, schedule=schedule)
-    sim.bin(api.cells_to_device(work["cells"]))
+    # the workload's largest cell bounds the cells: planned on the device, no sync
+    sim.bin(api.cells_to_device(work["cells"]), max_cell=int(np.diff(work["cells"]["cell_start"]).max()))
     tuned = None
     if schedule == "batched":
         tuned = choose_schedule(sim, 0.0, EVENTS_PER_CELL)

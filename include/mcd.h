@@ -18,10 +18,19 @@
  *    non-owning views and never frees them.  They must outlive the context.
  *  - All device work is enqueued on the caller's HIP stream given to
  *    mcd_init; functions marked "async" return before the work completes.
- *  - The library allocates its own device workspace (hipMalloc): in mcd_init
- *    and mcd_bin, and on first use in mcd_tune, mcd_set_gas_grid,
- *    mcd_sigma_hist and mcd_snapshot.  mcd_step allocates nothing.  mcd_free
- *    frees it all.
+ *  - Device memory beyond the particles is the caller's too: one workspace
+ *    of mcd_workspace_size bytes (e.g. a torch uint8 tensor), given to
+ *    mcd_init, holds the grid, the binning buffers, the cell lists of the
+ *    batched schedule, the device counters, the tuning backups and the
+ *    histogram edges.  mcd_init, mcd_bin, mcd_rates, mcd_row_sums, mcd_step,
+ *    mcd_tune, mcd_set_schedule and mcd_sigma_hist allocate no device
+ *    memory.  The two optional features whose size only their own call
+ *    fixes allocate at that call and free in mcd_free: the gas grid's nodes
+ *    (mcd_set_gas_grid) and the snapshot staging (mcd_snapshot, first call
+ *    or a larger field set).
+ *  - Largest cell: 2048 particles in the mixed form, 1536 in FP64 (a
+ *    four-wave team's particle records must fit the 160 KB of LDS); larger
+ *    cells are rejected with MCD_EINVAL.
  *  - Every function returns an mcd_status; no C++ exception crosses the ABI.
  *    After an error, mcd_last_error(ctx) describes it.  Kernels that detect
  *    an anomaly (a NaN or infinite rate, a non-positive mass or volume) set a
@@ -124,7 +133,8 @@ typedef struct {
   int32_t precision;    /* MCD_FP64 | MCD_MIXED */
   int32_t schedule;     /* MCD_SCHED_PLAIN | MCD_SCHED_BATCHED */
   int32_t frag_mode;    /* MCD_FRAG_*: how the relative velocity decides fragmentation */
-  int32_t pad;
+  int32_t max_cells;    /* most cells of an explicit grid this context will bin
+                           (0 = n_r * n_z); sizes the workspace's cell lists */
   double frag_width;    /* MCD_FRAG_RAMP: relative width w of the ramp, 0 < w <= 1 */
 } mcd_params;
 
@@ -140,6 +150,8 @@ typedef struct {
 
 typedef struct {
   int32_t n_cells;
+  int32_t max_cell;          /* upper bound on any cell's particle count (<= 2048), or 0:
+                                the library measures the sizes (one synchronisation) */
   const int32_t *cell_start; /* [n_cells + 1] device; member ranges into order */
   const int32_t *order;      /* [cell_start[n_cells]] device; particle indices, each cell's
                                 members in the order that defines cumulative rates */
@@ -160,25 +172,49 @@ typedef struct {
 
 typedef struct mcd_ctx mcd_ctx;
 
-/* Create a context.  Validates params (MCD_EINVAL on NaN, non-positive
- * physical constants, n_r*n_z > N in adaptive mode, n_comp out of range,
- * comp == NULL with n_comp > 0), records the particle views and the stream
- * (a hipStream_t; NULL = the null stream), and allocates the workspace.
- * Makes no kernel launch.  *out is set only on MCD_OK. */
+/* Bytes of device workspace a context needs for n particles (the paper,
+ * Summary: N representative particles in an adaptive grid of n_r x n_z
+ * equal-count cells, or explicit cells up to params->max_cells): the grid,
+ * the binning buffers, the batched schedule's cell lists, the device
+ * counters, the tuning backups and 2^16 histogram edges.  About 70 bytes per
+ * particle plus 12 per cell (more when a radial zone can exceed 8192
+ * particles).  MCD_EINVAL on bad params or n outside [1, 2^31). */
+mcd_status mcd_workspace_size(const mcd_params *params, int64_t n, size_t *bytes);
+
+/* Create a context for the paper's problem (Summary): the static power-law
+ * disk and collision physics of params over the caller's N representative
+ * particles.  Validates params (MCD_EINVAL on NaN, non-positive physical
+ * constants, n_comp out of range, comp == NULL with n_comp > 0) and the
+ * workspace (MCD_EINVAL if NULL or smaller than mcd_workspace_size), records
+ * the particle views, the stream (a hipStream_t; NULL = the null stream) and
+ * the workspace (device memory owned by the caller, which must outlive the
+ * context; the library never frees it), and enqueues the clearing of the
+ * device counters.  Allocates no device memory.  *out is set only on MCD_OK. */
 mcd_status mcd_init(const mcd_params *params, const mcd_particles *particles, void *hip_stream,
-                    mcd_ctx **out);
+                    void *workspace, size_t ws_bytes, mcd_ctx **out);
 
 /* Bin particles into cells (paper, Summary: adaptive grid of equal-count
  * cells).  explicit_or_null == NULL: adaptive binning of the active
  * particles into n_r radial zones of equal count by rank of (r, index), each
  * split into n_z cells of equal count by rank of (z, index), with the floor
  * rule for uneven counts; members of a cell are listed by ascending (z,
- * index); gas state at the cell centre from the power-law disk.  Async.
- * Otherwise: use the caller's explicit cells (device arrays are copied;
- * the call synchronises once to plan the schedule). */
+ * index); gas state at the cell centre from the power-law disk.  Async;
+ * MCD_EINVAL if n_r * n_z exceeds N or a cell could exceed the largest cell.
+ * Otherwise the caller's explicit cells: the library keeps non-owning views
+ * of cell_start, order and gas, which must stay valid and unchanged while
+ * this grid is in use (until the next mcd_bin or mcd_free), and plans the
+ * batched schedule on the device without copying to the host.  With
+ * max_cell > 0 the call is async and the grid is validated on the device:
+ * a grid whose cell_start starts below 0 or decreases, a cell above
+ * max_cell or a member index outside [0, N) is not collided and the next
+ * syncing call (mcd_get_stats) returns MCD_EDEVICE.  With max_cell == 0
+ * the call synchronises once to measure the cells and returns MCD_EINVAL
+ * for such a grid.  MCD_EINVAL also if n_cells exceeds the workspace's
+ * cells (params->max_cells) or max_cell exceeds the largest cell. */
 mcd_status mcd_bin(mcd_ctx *ctx, const mcd_cells *explicit_or_null);
 
-/* Rate matrix of one cell (test path): r_out[i*ld + j] = r_ij, the rate at
+/* Rate matrix of one cell (test path; the swarm rates of Zsom & Dullemond
+ * 2008, which the paper's Summary adopts): r_out[i*ld + j] = r_ij, the rate at
  * which representative particle i collides with a body of swarm j, computed
  * by the same pair code as the collision kernel in the context's precision
  * and returned as FP64 (device pointer, n_c x n_c with leading dimension ld
@@ -199,8 +235,10 @@ mcd_status mcd_rates(mcd_ctx *ctx, int32_t cell, double *r_out, int64_t ld, doub
  * no particle changes.  Async; test path.  MCD_ESTATE before mcd_bin. */
 mcd_status mcd_row_sums(mcd_ctx *ctx, double *out);
 
-/* Advance n_steps global steps of length dt [s]: (re)bin when the grid is
- * adaptive, collide every cell, transport.  Inside a cell, events run until
+/* Advance n_steps global steps of length dt [s] (the paper, Summary: bin
+ * into the adaptive grid, collide inside every cell, transport radially and
+ * vertically): (re)bin when the grid is adaptive, collide every cell,
+ * transport.  Allocates nothing.  Inside a cell, events run until
  * the next waiting time would pass dt (dt > 0) and/or max_events_per_cell
  * events are done (> 0); at least one limit must be set.  Async.  With the
  * batched schedule and n_steps > 1 one step is captured as a HIP graph
@@ -268,7 +306,9 @@ mcd_status mcd_set_gas_grid(mcd_ctx *ctx, const double *r_nodes, int32_t n_gr,
  * m_edges[l] <= m < m_edges[l+1], divided by the annulus area
  * pi (r_edges[k+1]^2 - r_edges[k]^2) (area 1 in column mode, where M is per
  * unit area): g/cm^2 per mass bin.  count [n_rb*n_mb]: device uint32, the
- * representative particles per bin, or NULL.  Async on the context stream.
+ * representative particles per bin, or NULL.  The edges go to the
+ * workspace (at most 2^16 in all); the call synchronises the stream first
+ * (no earlier upload still reads the host copy), then runs async.
  * The FP64 sums follow the order of device atomics (results may differ by
  * a relative count * 2^-52 between runs).  MCD_EINVAL on bad edges or
  * n_rb * n_mb outside [1, 2^24]. */
@@ -300,8 +340,10 @@ mcd_status mcd_snapshot(mcd_ctx *ctx, uint32_t fields, void *host_dst, size_t by
 /* Block until the snapshot with this ticket is in host memory. */
 mcd_status mcd_snapshot_wait(mcd_ctx *ctx, int64_t ticket);
 
-/* Copy the counters to the host (synchronises) and report the sticky
- * device flag as MCD_EDEVICE. */
+/* Copy the counters to the host (synchronises): collisions by outcome (the
+ * paper, Summary: sticking, erosion and fragmentation), steps, simulated
+ * time, active particles, the grid's cells and largest cell; report the
+ * sticky device flag as MCD_EDEVICE (mcd_last_error names its cause). */
 mcd_status mcd_get_stats(mcd_ctx *ctx, mcd_stats *host_out);
 
 /* Copy the current grid into caller device buffers (any may be NULL):

@@ -26,7 +26,7 @@ GAS_FIELDS = 6
 GEOM_FIELDS = 5
 
 # every function declared in include/mcd.h
-EXPORTS = ("mcd_init", "mcd_bin", "mcd_rates", "mcd_row_sums", "mcd_step", "mcd_tune", "mcd_set_schedule",
+EXPORTS = ("mcd_workspace_size", "mcd_init", "mcd_bin", "mcd_rates", "mcd_row_sums", "mcd_step", "mcd_tune", "mcd_set_schedule",
            "mcd_set_gas_grid", "mcd_sigma_hist", "mcd_snapshot_bytes", "mcd_snapshot", "mcd_snapshot_wait",
            "mcd_get_stats", "mcd_get_cells", "mcd_set_event_log", "mcd_philox", "mcd_last_error",
            "mcd_free")
@@ -39,7 +39,7 @@ class Params(C.Structure):
         ("kernel", C.c_int32), ("n_r", C.c_int32), ("n_z", C.c_int32), ("column", C.c_int32),
         ("flags", C.c_uint32), ("n_comp", C.c_int32), ("seed", C.c_uint64),
         ("precision", C.c_int32), ("schedule", C.c_int32), ("frag_mode", C.c_int32),
-        ("pad", C.c_int32), ("frag_width", C.c_double)]
+        ("max_cells", C.c_int32), ("frag_width", C.c_double)]
 
 
 FRAG_MODES = {"sharp": 0, "ramp": 1, "maxwell": 2}
@@ -52,8 +52,8 @@ class Particles(C.Structure):
 
 
 class Cells(C.Structure):
-    _fields_ = [("n_cells", C.c_int32), ("cell_start", C.c_void_p), ("order", C.c_void_p),
-                ("gas", C.c_void_p)]
+    _fields_ = [("n_cells", C.c_int32), ("max_cell", C.c_int32), ("cell_start", C.c_void_p),
+                ("order", C.c_void_p), ("gas", C.c_void_p)]
 
 
 class TuneResult(C.Structure):
@@ -81,7 +81,9 @@ def load() -> C.CDLL:
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, u32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32
     sig = {
-        "mcd_init": (i32, [C.POINTER(Params), C.POINTER(Particles), vp, C.POINTER(vp)]),
+        "mcd_workspace_size": (i32, [C.POINTER(Params), i64, C.POINTER(C.c_size_t)]),
+        "mcd_init": (i32, [C.POINTER(Params), C.POINTER(Particles), vp, vp, C.c_size_t,
+                           C.POINTER(vp)]),
         "mcd_bin": (i32, [vp, C.POINTER(Cells)]),
         "mcd_rates": (i32, [vp, i32, vp, i64, vp]),
         "mcd_row_sums": (i32, [vp, vp]),
@@ -108,7 +110,8 @@ def load() -> C.CDLL:
     return L
 
 
-def make_params(d: dict, precision: str = "mixed", schedule: str = "batched") -> Params:
+def make_params(d: dict, precision: str = "mixed", schedule: str = "batched",
+                max_cells: int = 0) -> Params:
     p = Params()
     for name, _ in Params._fields_:
         if name == "kernel":
@@ -125,8 +128,8 @@ def make_params(d: dict, precision: str = "mixed", schedule: str = "batched") ->
             p.frag_mode = FRAG_MODES[fm] if isinstance(fm, str) else int(fm)
         elif name == "frag_width":
             p.frag_width = d.get("frag_width", 0.0)
-        elif name == "pad":
-            pass
+        elif name == "max_cells":
+            p.max_cells = int(max_cells)
         else:
             setattr(p, name, d[name])
     return p

@@ -34,11 +34,13 @@ class Simulation:
     """One context of the collision step over caller-owned particle tensors.
 
     particles: dict of device tensors r, z, m, M (float64 [N]), active
-    (uint8 [N]) and optionally comp (float32 [n_comp, N]).
+    (uint8 [N]) and optionally comp (float32 [n_comp, N]).  The library's
+    device workspace is a torch tensor of this object (mcd_workspace_size
+    bytes), sized for explicit grids of up to max_cells cells (default N).
     """
 
     def __init__(self, params: dict, particles: dict, precision: str = "mixed",
-                 schedule: str = "batched", stream=None):
+                 schedule: str = "batched", stream=None, max_cells: int | None = None):
         self.lib = _lib.load()
         self.params = dict(params)
         self.t = {k: _dev(particles[k], torch.float64, k) for k in ("r", "z", "m", "M")}
@@ -47,15 +49,24 @@ class Simulation:
         if comp is not None:
             self.t["comp"] = _dev(comp, torch.float32, "comp")
         self.N = self.t["m"].numel()
-        self._p = _lib.make_params(params, precision, schedule)
+        # explicit grids of up to max_cells cells (default: one per particle)
+        if max_cells is None:
+            max_cells = min(self.N, 1 << 24)
+        self._p = _lib.make_params(params, precision, schedule, max_cells)
         self._parts = _lib.Particles(
             self.N, self.t["r"].data_ptr(), self.t["z"].data_ptr(), self.t["m"].data_ptr(),
             self.t["M"].data_ptr(), self.t["active"].data_ptr(),
             self.t["comp"].data_ptr() if comp is not None else None)
         self.stream = stream
+        nbytes = C.c_size_t()
+        st = self.lib.mcd_workspace_size(C.byref(self._p), self.N, C.byref(nbytes))
+        if st != 0:
+            raise MCDError(st, "mcd_workspace_size rejected the parameters")
+        # the library's device workspace: caller-owned torch memory
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.t["m"].device)
         ctx = C.c_void_p()
         st = self.lib.mcd_init(C.byref(self._p), C.byref(self._parts), _stream_handle(stream),
-                               C.byref(ctx))
+                               self.workspace.data_ptr(), nbytes.value, C.byref(ctx))
         if st != 0:
             raise MCDError(st, "mcd_init rejected the parameters or particles")
         self.ctx = ctx
@@ -66,15 +77,24 @@ class Simulation:
             msg = self.lib.mcd_last_error(self.ctx)
             raise MCDError(st, f"{what}: {msg.decode() if msg else ''}")
 
-    def bin(self, cells: dict | None = None) -> None:
+    def bin(self, cells: dict | None = None, max_cell: int | None = None) -> None:
+        """Adaptive binning (cells None), or the given explicit cells: device
+        tensors cell_start, order, gas, kept alive here while the grid is in
+        use.  max_cell: an upper bound on the cells' sizes (async planning),
+        default cells.get("max_cell", 0) (the library measures, one sync)."""
         if cells is None:
             self._check(self.lib.mcd_bin(self.ctx, None), "mcd_bin")
+            self._grid = None
             return
         cs = _dev(cells["cell_start"], torch.int32, "cell_start")
         order = _dev(cells["order"], torch.int32, "order")
         gas = _dev(cells["gas"], torch.float64, "gas")
-        c = _lib.Cells(cs.numel() - 1, cs.data_ptr(), order.data_ptr(), gas.data_ptr())
+        if max_cell is None:
+            max_cell = int(cells.get("max_cell", 0))
+        c = _lib.Cells(cs.numel() - 1, int(max_cell), cs.data_ptr(), order.data_ptr(),
+                       gas.data_ptr())
         self._check(self.lib.mcd_bin(self.ctx, C.byref(c)), "mcd_bin")
+        self._grid = (cs, order, gas)   # the library keeps views of these
 
     def step(self, dt: float, max_events: int = 0, n_steps: int = 1) -> None:
         self._check(self.lib.mcd_step(self.ctx, float(dt), int(max_events), int(n_steps)), "mcd_step")

@@ -635,6 +635,8 @@ hipError_t launch_binning(const Model &P, int n_r, int n_z, const double *r, con
   k_fix_ties<<<g1, 256, 0, s>>>(b.k32[cur], b.flag, r, N, state, b.by_r);
   // 2. rank by (z, index) inside each zone
   const int64_t zone_max = (N + n_r - 1) / n_r;  // no zone holds more
+  if (zone_max > kZoneSortMax && (b.keys[0] == nullptr || b.zone == nullptr))
+    return hipErrorInvalidValue;  // the workspace holds no buffers of the global path
   if (zone_max <= kZoneSortMax) {
     const int Pz = zone_sort_size(zone_max);
     const size_t lds = (size_t)Pz * 2 * sizeof(uint64_t);  // keys, then full bits for the runs

@@ -1,10 +1,11 @@
-// capi.hip -- the C ABI declared in include/mcd.h: argument validation,
-// workspace, cell schedules, the step loop and its HIP-graph replay.
+// capi.hip -- the C ABI declared in include/mcd.h: argument validation, the
+// caller's workspace, cell schedules, the step loop and its HIP-graph replay.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -15,19 +16,101 @@
 
 using namespace mcd;
 
+namespace {
+
+constexpr int kSmallLimit = 512;      // largest single-wave cell a schedule may choose
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
+constexpr size_t kAlign = 256;        // alignment of every workspace array
+constexpr int64_t kMaxEdges = 1 << 16;  // histogram edges held in the workspace
+constexpr uint32_t kKnownFlags = DV_BROWNIAN | DV_TURB | DV_RADIAL | DV_AZIMUTHAL | DV_SETTLING |
+                                 TR_DRIFT | TR_SETTLE | TR_MIX_R | TR_MIX_Z | COAG;
+
+// byte offsets of the workspace arrays (mcd_workspace_size, mcd_init)
+struct Layout {
+  size_t state, sbak, plan;                   // DevState, its tuning backup, Plan
+  size_t cs, order, gas, geom;                // the adaptive grid
+  size_t big, small, hist, cursor;            // cell lists and their planning
+  size_t mbak, cbak;                          // tuning backups of m and comp
+  size_t edges;                               // histogram edges
+  size_t k32[2], vals[2], flag, bs, part, by_r, hist_r, digit, k64[2], zone;  // binning
+  size_t total;
+  int64_t cells_adaptive, cells_cap;
+  int tiles;
+  bool global_z;
+};
+
+Layout layout_for(const mcd_params &p, int64_t N) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (std::max<size_t>(bytes, 1) + kAlign - 1) / kAlign * kAlign;
+    return o;
+  };
+  const int64_t na = (int64_t)p.n_r * p.n_z;
+  L.cells_adaptive = na;
+  L.cells_cap = std::max<int64_t>(std::max<int64_t>(na, p.max_cells), 1);
+  const size_t n = (size_t)N;
+  L.state = take(sizeof(DevState));
+  L.sbak = take(sizeof(DevState));
+  L.plan = take(sizeof(Plan));
+  L.cs = take(((size_t)na + 1) * sizeof(int32_t));
+  L.order = take(n * sizeof(int32_t));
+  L.gas = take((size_t)na * MCD_GAS_FIELDS * sizeof(double));
+  L.geom = take((size_t)na * MCD_GEOM_FIELDS * sizeof(double));
+  L.big = take((size_t)L.cells_cap * sizeof(int32_t));
+  L.small = take((size_t)L.cells_cap * sizeof(int32_t));
+  L.hist = take(kPlanBuckets * sizeof(uint32_t));
+  L.cursor = take(kPlanBuckets * sizeof(uint32_t));
+  L.mbak = take(n * sizeof(double));
+  L.cbak = take((size_t)p.n_comp * n * sizeof(float));
+  L.edges = take((size_t)kMaxEdges * sizeof(double));
+  L.tiles = radix_tiles(N);
+  for (int k = 0; k < 2; ++k) {
+    L.k32[k] = take(n * sizeof(uint32_t));
+    L.vals[k] = take(n * sizeof(int32_t));
+  }
+  L.flag = take(n);
+  L.bs = take(sizeof(BinState));
+  L.part = take((size_t)3 * kMinmaxParts * sizeof(uint64_t));
+  L.by_r = take(n * sizeof(int32_t));
+  L.hist_r = take((size_t)256 * L.tiles * sizeof(uint32_t));
+  L.digit = take(256 * sizeof(uint32_t));
+  // zones above the LDS zone sort take the global radix path by z
+  L.global_z = p.n_r >= 1 && (N + p.n_r - 1) / p.n_r > kZoneSortMax;
+  if (L.global_z) {
+    L.k64[0] = take(n * sizeof(uint64_t));
+    L.k64[1] = take(n * sizeof(uint64_t));
+    L.zone = take(n * sizeof(int32_t));
+  }
+  L.total = off + kAlign;  // room to align the caller's base address
+  return L;
+}
+
+}  // namespace
+
 struct mcd_ctx {
   mcd_params prm{};
   Model model{};
   mcd_particles part{};
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
+  Layout L{};
+  char *ws = nullptr;           // the caller's workspace, aligned
   bool adaptive = false, have_cells = false;
-  int32_t n_cells = 0, max_cell = 0, cells_alloc = 0;
-  int64_t order_alloc = 0;
-  int32_t *d_cell_start = nullptr, *d_order = nullptr, *d_big = nullptr, *d_small = nullptr;
-  double *d_gas = nullptr, *d_geom = nullptr;
-  int n_big = 0, n_small = 0, big_cap = 0, small_cap = 0;
-  std::vector<int32_t> h_cell_start;  // explicit grids
+  int32_t n_cells = 0;
+  // the grid in use: the library's adaptive grid or the caller's explicit one
+  const int32_t *cell_start = nullptr, *order = nullptr;
+  const double *gas = nullptr;
+  int32_t *g_cell_start = nullptr, *g_order = nullptr;  // adaptive grid (workspace)
+  double *g_gas = nullptr, *g_geom = nullptr;
+  // largest cell: the bound the caps follow (adaptive: the floor rule's;
+  // explicit: the caller's, or measured when the caller gave none)
+  int32_t bound = 0;
+  bool exact = false;           // explicit grid without a bound: caps from measured sizes
+  int32_t max_big = 0, max_small = 0, max_cell = 0;
+  int big_cap = 0, small_cap = 0;
+  PlanBuffers pb{};
   BinBuffers bb{};
   DevState *d_state = nullptr;
   int32_t *evlog = nullptr;
@@ -43,7 +126,6 @@ struct mcd_ctx {
   int small_max = 256;
   int grid_per_cu = 0;
   int cus = 0;
-  std::vector<int32_t> sizes;  // particle count of every cell of the grid
   // snapshots: two device staging buffers filled in stream order, each
   // copied to the caller's host memory on copy_stream
   hipStream_t copy_stream = nullptr;
@@ -55,22 +137,14 @@ struct mcd_ctx {
   double *d_grid = nullptr;     // gridded gas: lr, zn, lrho, lT, lA, lS back to back
   std::vector<double> h_grid;
   std::vector<double> h_edges;  // histogram bin edges (host copy, read by the async upload)
-  double *d_edges = nullptr;
-  size_t edges_cap = 0;
-  double *d_mbak = nullptr;    // tuning backups of m, comp and the device state
+  double *d_edges = nullptr;    // workspace
+  double *d_mbak = nullptr;     // tuning backups of m, comp and the device state (workspace)
   float *d_cbak = nullptr;
   DevState *d_sbak = nullptr;
   std::string err;
 };
 
 namespace {
-
-constexpr int kSmallLimit = 512;      // largest single-wave cell a schedule may choose
-constexpr int kBigMax = 2048;         // largest cell of the batched schedule
-constexpr int kPlainMax = 2048;       // largest cell of the plain schedule
-constexpr size_t kLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
-constexpr uint32_t kKnownFlags = DV_BROWNIAN | DV_TURB | DV_RADIAL | DV_AZIMUTHAL | DV_SETTLING |
-                                 TR_DRIFT | TR_SETTLE | TR_MIX_R | TR_MIX_Z | COAG;
 
 mcd_status fail(mcd_ctx *c, mcd_status s, const std::string &msg) {
   if (c) c->err = msg;
@@ -120,6 +194,7 @@ std::string check_params(const mcd_params &p) {
   if (p.kernel < MCD_K_PHYSICAL || p.kernel > MCD_K_LINEAR) return "unknown kernel";
   if (p.n_r < 1 || p.n_z < 1) return "n_r and n_z must be >= 1";
   if ((int64_t)p.n_r * p.n_z > (1 << 24)) return "too many cells";
+  if (p.max_cells < 0 || p.max_cells > (1 << 24)) return "max_cells must be in [0, 2^24]";
   if (p.flags & ~kKnownFlags) return "unknown flag bits";
   if (p.n_comp < 0 || p.n_comp > MCD_MAX_COMP) return "n_comp must be in [0, 8]";
   if (p.precision != MCD_FP64 && p.precision != MCD_MIXED) return "unknown precision";
@@ -169,115 +244,103 @@ void drop_graph(mcd_ctx *c) {
   c->g_valid = false;
 }
 
-void free_grid(mcd_ctx *c) {
-  dfree(c->d_cell_start);
-  dfree(c->d_order);
-  dfree(c->d_gas);
-  dfree(c->d_geom);
-  dfree(c->d_big);
-  dfree(c->d_small);
-  c->d_cell_start = c->d_order = c->d_big = c->d_small = nullptr;
-  c->d_gas = c->d_geom = nullptr;
-  c->cells_alloc = 0;
-  c->order_alloc = 0;
-}
-
-mcd_status alloc_grid(mcd_ctx *c, int32_t n_cells, int64_t n_order) {
-  if (n_cells <= c->cells_alloc && n_order <= c->order_alloc) return MCD_OK;
-  free_grid(c);
-  if (dalloc(&c->d_cell_start, (size_t)n_cells + 1) != hipSuccess ||
-      dalloc(&c->d_order, (size_t)n_order) != hipSuccess ||
-      dalloc(&c->d_gas, (size_t)n_cells * MCD_GAS_FIELDS) != hipSuccess ||
-      dalloc(&c->d_geom, (size_t)n_cells * MCD_GEOM_FIELDS) != hipSuccess ||
-      dalloc(&c->d_big, (size_t)n_cells) != hipSuccess ||
-      dalloc(&c->d_small, (size_t)n_cells) != hipSuccess) {
-    free_grid(c);
-    return fail(c, MCD_ENOMEM, "device allocation of the grid failed");
-  }
-  c->cells_alloc = n_cells;
-  c->order_alloc = n_order;
-  return MCD_OK;
-}
-
-void free_binning(BinBuffers &b) {
-  void *const all[] = {b.keys[0], b.keys[1], b.k32[0], b.k32[1], b.vals[0], b.vals[1], b.flag,
-                       b.bs,      b.part,    b.by_r,   b.zone,   b.hist,   b.digit_tot};
-  for (void *p : all) dfree(p);
-  b = BinBuffers{};
-}
-
-mcd_status alloc_binning(mcd_ctx *c, int64_t N) {
-  if (c->bb.cap >= N) return MCD_OK;
+// carve the arrays of the layout out of the (aligned) workspace
+void carve(mcd_ctx *c) {
+  const Layout &L = c->L;
+  char *w = c->ws;
+  c->d_state = (DevState *)(w + L.state);
+  c->d_sbak = (DevState *)(w + L.sbak);
+  c->pb.plan = (Plan *)(w + L.plan);
+  c->g_cell_start = (int32_t *)(w + L.cs);
+  c->g_order = (int32_t *)(w + L.order);
+  c->g_gas = (double *)(w + L.gas);
+  c->g_geom = (double *)(w + L.geom);
+  c->pb.big = (int32_t *)(w + L.big);
+  c->pb.small = (int32_t *)(w + L.small);
+  c->pb.hist = (uint32_t *)(w + L.hist);
+  c->pb.cursor = (uint32_t *)(w + L.cursor);
+  c->d_mbak = (double *)(w + L.mbak);
+  c->d_cbak = c->prm.n_comp > 0 ? (float *)(w + L.cbak) : nullptr;
+  c->d_edges = (double *)(w + L.edges);
   BinBuffers &b = c->bb;
-  free_binning(b);
-  const int tiles = radix_tiles(N);
-  if (dalloc(&b.keys[0], N) != hipSuccess || dalloc(&b.keys[1], N) != hipSuccess ||
-      dalloc(&b.k32[0], N) != hipSuccess || dalloc(&b.k32[1], N) != hipSuccess ||
-      dalloc(&b.vals[0], N) != hipSuccess || dalloc(&b.vals[1], N) != hipSuccess ||
-      dalloc(&b.flag, N) != hipSuccess || dalloc(&b.bs, 1) != hipSuccess ||
-      dalloc(&b.part, (size_t)3 * kMinmaxParts) != hipSuccess ||
-      dalloc(&b.by_r, N) != hipSuccess || dalloc(&b.zone, N) != hipSuccess ||
-      dalloc(&b.hist, (size_t)256 * tiles) != hipSuccess ||
-      dalloc(&b.digit_tot, 256) != hipSuccess)
-    return fail(c, MCD_ENOMEM, "device allocation of the binning workspace failed");
-  b.cap = N;
-  b.tiles = tiles;
-  return MCD_OK;
+  for (int k = 0; k < 2; ++k) {
+    b.k32[k] = (uint32_t *)(w + L.k32[k]);
+    b.vals[k] = (int32_t *)(w + L.vals[k]);
+    b.keys[k] = L.global_z ? (uint64_t *)(w + L.k64[k]) : nullptr;
+  }
+  b.flag = (uint8_t *)(w + L.flag);
+  b.bs = (BinState *)(w + L.bs);
+  b.part = (uint64_t *)(w + L.part);
+  b.by_r = (int32_t *)(w + L.by_r);
+  b.zone = L.global_z ? (int32_t *)(w + L.zone) : nullptr;
+  b.hist = (uint32_t *)(w + L.hist_r);
+  b.digit_tot = (uint32_t *)(w + L.digit);
+  b.cap = c->part.n;
+  b.tiles = L.tiles;
 }
 
-// cell lists of the batched schedule: big cells (team of four waves) and
-// small cells (one wave), each largest first; ties keep the cell index order
-mcd_status plan_lists(mcd_ctx *c, const std::vector<int32_t> &sizes) {
-  std::vector<int32_t> big, small;
-  int32_t mb = 0, ms = 0;
-  c->sizes = sizes;
-  for (int32_t k = 0; k < (int32_t)sizes.size(); ++k) {
-    if (sizes[k] > c->small_max) {
-      big.push_back(k);
-      mb = std::max(mb, sizes[k]);
-    } else if (sizes[k] > 0) {
-      small.push_back(k);
-      ms = std::max(ms, sizes[k]);
-    }
-  }
-  auto by_size = [&](int32_t a, int32_t b) { return sizes[a] > sizes[b]; };
-  std::stable_sort(big.begin(), big.end(), by_size);
-  std::stable_sort(small.begin(), small.end(), by_size);
-  c->n_big = (int)big.size();
-  c->n_small = (int)small.size();
-  c->big_cap = mb > 0 ? (mb + 255) / 256 * 256 : 0;
-  c->small_cap = std::max(64, (ms + 63) / 64 * 64);
-  c->max_cell = std::max(mb, ms);
+// LDS region capacities of the batched (or plain) launch from the largest
+// cell of each list; EINVAL if a region does not fit the LDS
+mcd_status set_caps(mcd_ctx *c, int32_t max_big, int32_t max_small, int32_t max_cell) {
+  c->max_big = max_big;
+  c->max_small = max_small;
+  c->max_cell = max_cell;
+  c->big_cap = max_big > 0 ? (max_big + 255) / 256 * 256 : 0;
+  c->small_cap = std::max(64, (max_small + 63) / 64 * 64);
   // the plain schedule runs every cell on one four-wave workgroup
-  if (c->prm.schedule == MCD_SCHED_PLAIN) c->big_cap = std::max(256, (c->max_cell + 255) / 256 * 256);
+  if (c->prm.schedule == MCD_SCHED_PLAIN) c->big_cap = std::max(256, (max_cell + 255) / 256 * 256);
   const bool f64 = c->prm.precision == MCD_FP64;
   const size_t lds_big = f64 ? region_bytes<double>(c->big_cap, 4) : region_bytes<float>(c->big_cap, 4);
   const size_t lds_small = 4 * (f64 ? region_bytes<double>(c->small_cap, 1)
                                     : region_bytes<float>(c->small_cap, 1));
   const size_t lds = c->prm.schedule == MCD_SCHED_PLAIN ? lds_big : std::max(lds_big, lds_small);
   if (lds > kLdsBytes)
-    return fail(c, MCD_EINVAL, "largest cell does not fit the 160 KB LDS in this precision");
-  // in stream order, so that work already queued still sees the old lists
-  if (!big.empty())
-    MCD_HIP(c, hipMemcpyAsync(c->d_big, big.data(), big.size() * sizeof(int32_t),
-                              hipMemcpyHostToDevice, c->stream));
-  if (!small.empty())
-    MCD_HIP(c, hipMemcpyAsync(c->d_small, small.data(), small.size() * sizeof(int32_t),
-                              hipMemcpyHostToDevice, c->stream));
-  MCD_HIP(c, hipStreamSynchronize(c->stream));
+    return fail(c, MCD_EINVAL,
+                std::string("largest cell does not fit the 160 KB LDS in this precision (") +
+                    std::to_string(max_cell) + " particles; at most " +
+                    std::to_string(f64 ? kMaxCellFp64 : kMaxCell) + ")");
   return MCD_OK;
+}
+
+// plan the batched lists for the current grid and schedule on the device
+// (in stream order: work already queued still sees the old lists); the caps
+// follow the bound, or the measured sizes (one synchronisation) when the
+// caller of an explicit grid gave no bound
+mcd_status plan_lists(mcd_ctx *c) {
+  hipError_t e;
+  if (c->adaptive) {
+    e = launch_plan_uniform(c->n_cells, c->bound, c->small_max, c->pb, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "planning the cell lists");
+    const bool big = c->bound > c->small_max;
+    return set_caps(c, big ? c->bound : 0, big ? 0 : c->bound, c->bound);
+  }
+  e = launch_plan_explicit(c->cell_start, c->order, c->n_cells, c->part.n,
+                           c->exact ? kMaxCell : c->bound, c->small_max, c->pb, c->d_state,
+                           c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "planning the cell lists");
+  if (!c->exact) {
+    const bool big = c->bound > c->small_max;
+    return set_caps(c, big ? c->bound : 0, std::min(c->bound, c->small_max), c->bound);
+  }
+  Plan pl{};
+  MCD_HIP(c, hipMemcpyAsync(&pl, c->pb.plan, sizeof(Plan), hipMemcpyDeviceToHost, c->stream));
+  MCD_HIP(c, hipStreamSynchronize(c->stream));
+  if (pl.bad)
+    return fail(c, MCD_EINVAL,
+                "explicit cells rejected: cell_start must start >= 0 and not decrease, no cell "
+                "may exceed 2048 particles and every member index must be in [0, N)");
+  return set_caps(c, pl.max_big, pl.max_small, pl.max_cell);
 }
 
 CollideArgs collide_args(mcd_ctx *c, double dt, int64_t max_events) {
   CollideArgs a{};
   a.P = c->model;
-  a.cell_start = c->d_cell_start;
-  a.order = c->d_order;
-  a.gas = c->d_gas;
-  a.big_list = c->d_big;
-  a.small_list = c->d_small;
-  a.n_big = c->n_big;
-  a.n_small = c->n_small;
+  a.cell_start = c->cell_start;
+  a.order = c->order;
+  a.gas = c->gas;
+  a.big_list = c->pb.big;
+  a.small_list = c->pb.small;
+  a.plan = c->pb.plan;
   a.big_cap = c->big_cap;
   a.small_cap = c->small_cap;
   a.m = c->part.m;
@@ -299,8 +362,8 @@ bool transport_on(const mcd_ctx *c) {
 
 mcd_status enqueue_bin(mcd_ctx *c, hipStream_t s) {
   hipError_t e = launch_binning(c->model, c->prm.n_r, c->prm.n_z, c->part.r, c->part.z,
-                                c->part.active, c->part.n, c->bb, c->d_cell_start, c->d_order,
-                                c->d_geom, c->d_gas, c->d_state, s);
+                                c->part.active, c->part.n, c->bb, c->g_cell_start, c->g_order,
+                                c->g_geom, c->g_gas, c->d_state, s);
   if (e != hipSuccess) return hip_fail(c, e, "binning");
   return MCD_OK;
 }
@@ -324,13 +387,8 @@ mcd_status enqueue_step(mcd_ctx *c, double dt, int64_t max_events, hipStream_t s
   return MCD_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-mcd_status mcd_init(const mcd_params *params, const mcd_particles *particles, void *hip_stream,
-                    mcd_ctx **out) {
-  if (!params || !particles || !out) return MCD_EINVAL;
+std::string why_params(const mcd_params *params, const mcd_particles *particles) {
+  if (!params || !particles) return "params and particles must not be NULL";
   std::string why = check_params(*params);
   const mcd_particles &p = *particles;
   if (why.empty()) {
@@ -338,23 +396,44 @@ mcd_status mcd_init(const mcd_params *params, const mcd_particles *particles, vo
     else if (!p.r || !p.z || !p.m || !p.M || !p.active) why = "particle arrays must not be NULL";
     else if (params->n_comp > 0 && !p.comp) why = "comp must be given when n_comp > 0";
   }
-  if (!why.empty()) return MCD_EINVAL;
+  return why;
+}
+
+}  // namespace
+
+extern "C" {
+
+mcd_status mcd_workspace_size(const mcd_params *params, int64_t n, size_t *bytes) {
+  if (!params || !bytes || n <= 0 || n >= (int64_t)1 << 31) return MCD_EINVAL;
+  if (!check_params(*params).empty()) return MCD_EINVAL;
+  *bytes = layout_for(*params, n).total;
+  return MCD_OK;
+}
+
+mcd_status mcd_init(const mcd_params *params, const mcd_particles *particles, void *hip_stream,
+                    void *workspace, size_t ws_bytes, mcd_ctx **out) {
+  if (!out) return MCD_EINVAL;
+  if (!why_params(params, particles).empty()) return MCD_EINVAL;
+  const Layout L = layout_for(*params, particles->n);
+  if (!workspace || ws_bytes < L.total) return MCD_EINVAL;
   mcd_ctx *c = new (std::nothrow) mcd_ctx();
   if (!c) return MCD_ENOMEM;
   c->prm = *params;
   c->model = make_model(*params);
-  c->part = p;
+  c->part = *particles;
   if (params->n_comp == 0) c->part.comp = nullptr;
   c->stream = (hipStream_t)hip_stream;
+  c->L = L;
+  c->ws = (char *)(((uintptr_t)workspace + kAlign - 1) / kAlign * kAlign);
+  carve(c);
   hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipMalloc((void **)&c->d_state, sizeof(DevState));
-  if (e == hipSuccess) e = hipMemset(c->d_state, 0, sizeof(DevState));
+  if (e == hipSuccess) e = launch_clear_state(c->d_state, c->pb.plan, c->stream);
   int dev = 0;
   if (e == hipSuccess) e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) {
     mcd_free(c);
-    return e == hipErrorOutOfMemory ? MCD_ENOMEM : MCD_EHIP;
+    return MCD_EHIP;
   }
   *out = c;
   return MCD_OK;
@@ -365,9 +444,7 @@ mcd_status mcd_bin(mcd_ctx *c, const mcd_cells *cells) {
   if (!cells && c->adaptive && c->have_cells) {
     // re-binning on the same grid: the cell lists, buffers and any captured
     // step graph stay valid; only the binning kernels are enqueued
-    mcd_status st;
-    if ((st = enqueue_bin(c, c->stream)) != MCD_OK) return st;
-    return MCD_OK;
+    return enqueue_bin(c, c->stream);
   }
   drop_graph(c);
   if (!cells) {
@@ -376,60 +453,44 @@ mcd_status mcd_bin(mcd_ctx *c, const mcd_cells *cells) {
     if ((int64_t)nr * nz > N) return fail(c, MCD_EINVAL, "n_r * n_z exceeds the particle count");
     const int64_t zone_max = (N + nr - 1) / nr;
     const int32_t cell_max = (int32_t)((zone_max + nz - 1) / nz);
-    const int32_t limit = c->prm.schedule == MCD_SCHED_PLAIN ? kPlainMax : kBigMax;
-    if (cell_max > limit)
-      return fail(c, MCD_EINVAL, "cells would exceed " + std::to_string(limit) +
+    if (cell_max > kMaxCell)
+      return fail(c, MCD_EINVAL, "cells would exceed " + std::to_string(kMaxCell) +
                                      " particles; use more cells");
-    mcd_status st;
-    if ((st = alloc_grid(c, nr * nz, N)) != MCD_OK) return st;
-    if ((st = alloc_binning(c, N)) != MCD_OK) return st;
     c->adaptive = true;
+    c->have_cells = false;
     c->n_cells = nr * nz;
-    // equal-count cells differ by at most one particle: a single class
-    std::vector<int32_t> sizes((size_t)c->n_cells, cell_max);
-    if ((st = plan_lists(c, sizes)) != MCD_OK) return st;
+    c->cell_start = c->g_cell_start;
+    c->order = c->g_order;
+    c->gas = c->g_gas;
+    // equal-count cells differ by at most one particle: one class, bounded
+    // by the floor rule's largest cell
+    c->bound = cell_max;
+    c->exact = false;
+    mcd_status st;
+    if ((st = plan_lists(c)) != MCD_OK) return st;
     if ((st = enqueue_bin(c, c->stream)) != MCD_OK) return st;
     c->have_cells = true;
     return MCD_OK;
   }
-  // explicit cells
+  // explicit cells: non-owning views, validated and planned on the device
   const int32_t nc = cells->n_cells;
   if (nc < 1 || !cells->cell_start || !cells->order || !cells->gas)
     return fail(c, MCD_EINVAL, "explicit cells need n_cells >= 1 and device arrays");
-  std::vector<int32_t> cs((size_t)nc + 1);
-  MCD_HIP(c, hipMemcpy(cs.data(), cells->cell_start, cs.size() * sizeof(int32_t),
-                       hipMemcpyDeviceToHost));
-  if (cs[0] < 0) return fail(c, MCD_EINVAL, "cell_start[0] < 0");
-  std::vector<int32_t> sizes((size_t)nc);
-  for (int32_t k = 0; k < nc; ++k) {
-    sizes[k] = cs[k + 1] - cs[k];
-    if (sizes[k] < 0) return fail(c, MCD_EINVAL, "cell_start must be non-decreasing");
-  }
-  const int64_t n_order = cs[nc];
-  std::vector<int32_t> ord((size_t)std::max<int64_t>(n_order, 1));
-  if (n_order > 0)
-    MCD_HIP(c, hipMemcpy(ord.data(), cells->order, (size_t)n_order * sizeof(int32_t),
-                         hipMemcpyDeviceToHost));
-  for (int64_t k = cs[0]; k < n_order; ++k)
-    if (ord[k] < 0 || ord[k] >= c->part.n) return fail(c, MCD_EINVAL, "order index out of range");
-  const int32_t mx = sizes.empty() ? 0 : *std::max_element(sizes.begin(), sizes.end());
-  const int32_t limit = c->prm.schedule == MCD_SCHED_PLAIN ? kPlainMax : kBigMax;
-  if (mx > limit)
-    return fail(c, MCD_EINVAL, "a cell exceeds " + std::to_string(limit) + " particles");
-  mcd_status st;
-  if ((st = alloc_grid(c, nc, std::max<int64_t>(n_order, 1))) != MCD_OK) return st;
-  MCD_HIP(c, hipMemcpyAsync(c->d_cell_start, cells->cell_start, cs.size() * sizeof(int32_t),
-                            hipMemcpyDeviceToDevice, c->stream));
-  if (n_order > 0)
-    MCD_HIP(c, hipMemcpyAsync(c->d_order, cells->order, (size_t)n_order * sizeof(int32_t),
-                              hipMemcpyDeviceToDevice, c->stream));
-  MCD_HIP(c, hipMemcpyAsync(c->d_gas, cells->gas, (size_t)nc * MCD_GAS_FIELDS * sizeof(double),
-                            hipMemcpyDeviceToDevice, c->stream));
-  MCD_HIP(c, hipStreamSynchronize(c->stream));
+  if ((int64_t)nc > c->L.cells_cap)
+    return fail(c, MCD_EINVAL, "n_cells exceeds the workspace's cells (" +
+                                   std::to_string(c->L.cells_cap) + "; set max_cells)");
+  if (cells->max_cell < 0 || cells->max_cell > kMaxCell)
+    return fail(c, MCD_EINVAL, "max_cell must be in [0, " + std::to_string(kMaxCell) + "]");
   c->adaptive = false;
+  c->have_cells = false;
   c->n_cells = nc;
-  c->h_cell_start = cs;
-  if ((st = plan_lists(c, sizes)) != MCD_OK) return st;
+  c->cell_start = cells->cell_start;
+  c->order = cells->order;
+  c->gas = cells->gas;
+  c->bound = cells->max_cell;
+  c->exact = cells->max_cell == 0;
+  mcd_status st = plan_lists(c);
+  if (st != MCD_OK) return st;
   c->have_cells = true;
   return MCD_OK;
 }
@@ -439,9 +500,12 @@ mcd_status mcd_rates(mcd_ctx *c, int32_t cell, double *r_out, int64_t ld, double
   if (!c->have_cells) return fail(c, MCD_ESTATE, "mcd_rates before mcd_bin");
   if (cell < 0 || cell >= c->n_cells || !r_out) return fail(c, MCD_EINVAL, "bad cell or r_out");
   int32_t se[2];
-  MCD_HIP(c, hipMemcpyAsync(se, c->d_cell_start + cell, 2 * sizeof(int32_t),
-                            hipMemcpyDeviceToHost, c->stream));
+  Plan pl{};
+  MCD_HIP(c, hipMemcpyAsync(se, c->cell_start + cell, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                            c->stream));
+  MCD_HIP(c, hipMemcpyAsync(&pl, c->pb.plan, sizeof(Plan), hipMemcpyDeviceToHost, c->stream));
   MCD_HIP(c, hipStreamSynchronize(c->stream));
+  if (pl.bad) return fail(c, MCD_EINVAL, "the explicit grid failed validation");
   if (ld < se[1] - se[0]) return fail(c, MCD_EINVAL, "ld smaller than the cell size");
   hipError_t e = launch_rates_cell(collide_args(c, 0.0, 0), c->prm.precision, cell, r_out, ld,
                                    rowsum_out, c->stream);
@@ -510,11 +574,13 @@ mcd_status mcd_set_schedule(mcd_ctx *c, int32_t small_max, int32_t grid_per_cu) 
   c->small_max = small_max;
   c->grid_per_cu = grid_per_cu;
   if (c->have_cells) {
-    mcd_status st = plan_lists(c, c->sizes);
+    mcd_status st = plan_lists(c);
     if (st != MCD_OK) {
+      const std::string why = c->err;
       c->small_max = sm0;
       c->grid_per_cu = g0;
-      (void)plan_lists(c, c->sizes);
+      (void)plan_lists(c);
+      c->err = why;
       return st;
     }
   }
@@ -537,11 +603,6 @@ mcd_status mcd_tune(mcd_ctx *c, double dt, int64_t max_events, mcd_tune_result *
   if (!(c->prm.flags & COAG)) return MCD_OK;
   const int64_t N = c->part.n;
   const size_t ncomp = c->part.comp ? (size_t)c->prm.n_comp * (size_t)N : 0;
-  if (!c->d_mbak) {
-    if (dalloc(&c->d_mbak, (size_t)N) != hipSuccess || dalloc(&c->d_sbak, 1) != hipSuccess ||
-        (ncomp && dalloc(&c->d_cbak, ncomp) != hipSuccess))
-      return fail(c, MCD_ENOMEM, "device allocation of the tuning backups failed");
-  }
   hipStream_t s = c->stream;
   MCD_HIP(c, hipMemcpyAsync(c->d_mbak, c->part.m, (size_t)N * sizeof(double),
                             hipMemcpyDeviceToDevice, s));
@@ -563,11 +624,20 @@ mcd_status mcd_tune(mcd_ctx *c, double dt, int64_t max_events, mcd_tune_result *
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   hipError_t herr = hipEventCreate(&ev_a);
   if (herr == hipSuccess) herr = hipEventCreate(&ev_b);
+  // the lists of the schedule in force, read back (the tuner synchronises)
+  auto plan_key = [&](std::array<int, 4> &key) -> bool {
+    Plan pl{};
+    if (hipMemcpyAsync(&pl, c->pb.plan, sizeof(Plan), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return false;
+    key = {pl.n_big, pl.n_small, c->big_cap, c->small_cap};
+    return true;
+  };
   // time one collision launch per configuration, state restored before each
   auto trial = [&](int sm, int gpc, double &ms) -> bool {
     c->small_max = sm;
     c->grid_per_cu = gpc;
-    if (plan_lists(c, c->sizes) != MCD_OK) return false;  // does not fit this GPU
+    if (plan_lists(c) != MCD_OK) return false;  // does not fit this GPU
     for (int rep = 0; rep < 2 && herr == hipSuccess; ++rep) {
       herr = restore();
       if (herr == hipSuccess && rep == 1) herr = hipEventRecord(ev_a, s);
@@ -592,14 +662,16 @@ mcd_status mcd_tune(mcd_ctx *c, double dt, int64_t max_events, mcd_tune_result *
   if (trial(sm0, g0, t)) {
     best = t;
     out->ms_default = t;
-    if (g0 == 0) seen.push_back({c->n_big, c->n_small, c->big_cap, c->small_cap});
+    std::array<int, 4> key{};
+    if (g0 == 0 && plan_key(key)) seen.push_back(key);
   }
   const int sms[] = {0, 64, 128, 192, 256, 384, 512};
   for (int sm : sms) {
     if (herr != hipSuccess) break;
     c->small_max = sm;
-    if (plan_lists(c, c->sizes) != MCD_OK) continue;
-    const std::array<int, 4> key{c->n_big, c->n_small, c->big_cap, c->small_cap};
+    if (plan_lists(c) != MCD_OK) continue;
+    std::array<int, 4> key{};
+    if (!plan_key(key)) break;
     if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
     seen.push_back(key);
     if (trial(sm, 0, t) && (best == 0.0 || t < best)) {
@@ -620,7 +692,7 @@ mcd_status mcd_tune(mcd_ctx *c, double dt, int64_t max_events, mcd_tune_result *
   c->evlog = evlog;
   c->small_max = best_sm;
   c->grid_per_cu = best_g;
-  mcd_status st = plan_lists(c, c->sizes);
+  mcd_status st = plan_lists(c);
   if (herr == hipSuccess) herr = restore();
   if (herr == hipSuccess) herr = hipStreamSynchronize(s);
   drop_graph(c);
@@ -715,14 +787,10 @@ mcd_status mcd_sigma_hist(mcd_ctx *c, const double *r_edges, int32_t n_rb, const
   if (!increasing(r_edges, n_rb) || !increasing(m_edges, n_mb) || r_edges[0] < 0.0)
     return fail(c, MCD_EINVAL, "bin edges must be finite and strictly increasing, r_edges[0] >= 0");
   const size_t ne = (size_t)n_rb + 1 + (size_t)n_mb + 1;
-  if (ne > c->edges_cap) {
-    dfree(c->d_edges);
-    c->d_edges = nullptr;
-    c->edges_cap = 0;
-    if (dalloc(&c->d_edges, ne) != hipSuccess)
-      return fail(c, MCD_ENOMEM, "device allocation of the bin edges failed");
-    c->edges_cap = ne;
-  }
+  if ((int64_t)ne > kMaxEdges)
+    return fail(c, MCD_EINVAL, "at most " + std::to_string(kMaxEdges) + " bin edges in all");
+  // the previous histogram's upload must be done before its host copy is replaced
+  MCD_HIP(c, hipStreamSynchronize(c->stream));
   c->h_edges.assign(r_edges, r_edges + n_rb + 1);
   c->h_edges.insert(c->h_edges.end(), m_edges, m_edges + n_mb + 1);
   MCD_HIP(c, hipMemcpyAsync(c->d_edges, c->h_edges.data(), ne * sizeof(double),
@@ -829,13 +897,19 @@ mcd_status mcd_get_stats(mcd_ctx *c, mcd_stats *o) {
   o->events = (int64_t)s.events;
   for (int k = 0; k < 4; ++k) o->outcomes[k] = (int64_t)s.outcomes[k];
   o->steps = s.step;
-  o->n_active = c->adaptive ? s.n_active : (c->have_cells ? c->h_cell_start.back() : 0);
+  o->n_active = c->have_cells ? s.n_active : 0;
   o->t_sim = s.t_sim;
   o->device_flags = s.flags;
   o->n_cells = c->n_cells;
   o->max_cell = c->max_cell;
   if (s.flags) {
-    c->err = "device anomaly flags 0x" + std::to_string(s.flags);
+    char hex[16];
+    std::snprintf(hex, sizeof(hex), "%x", s.flags);
+    c->err = std::string("device anomaly flags 0x") + hex;
+    if (s.flags & FLAG_BAD_GRID)
+      c->err += ": explicit cells rejected on the device (cell_start must start >= 0 and not "
+                "decrease, no cell above max_cell, member indices in [0, N)); nothing collided";
+    if (s.flags & FLAG_CAPACITY) c->err += ": a cell exceeded its launch's capacity and was skipped";
     return MCD_EDEVICE;
   }
   return MCD_OK;
@@ -846,21 +920,21 @@ mcd_status mcd_get_cells(mcd_ctx *c, int32_t *cell_start, int32_t *order, double
   if (!c) return MCD_EINVAL;
   if (!c->have_cells) return fail(c, MCD_ESTATE, "no grid yet");
   int32_t n_order = 0;
-  MCD_HIP(c, hipMemcpyAsync(&n_order, c->d_cell_start + c->n_cells, sizeof(int32_t),
+  MCD_HIP(c, hipMemcpyAsync(&n_order, c->cell_start + c->n_cells, sizeof(int32_t),
                             hipMemcpyDeviceToHost, c->stream));
   MCD_HIP(c, hipStreamSynchronize(c->stream));
   const size_t nc = (size_t)c->n_cells;
   if (cell_start)
-    MCD_HIP(c, hipMemcpyAsync(cell_start, c->d_cell_start, (nc + 1) * sizeof(int32_t),
+    MCD_HIP(c, hipMemcpyAsync(cell_start, c->cell_start, (nc + 1) * sizeof(int32_t),
                               hipMemcpyDeviceToDevice, c->stream));
   if (order && n_order > 0)
-    MCD_HIP(c, hipMemcpyAsync(order, c->d_order, (size_t)n_order * sizeof(int32_t),
+    MCD_HIP(c, hipMemcpyAsync(order, c->order, (size_t)n_order * sizeof(int32_t),
                               hipMemcpyDeviceToDevice, c->stream));
   if (geom && c->adaptive)
-    MCD_HIP(c, hipMemcpyAsync(geom, c->d_geom, nc * MCD_GEOM_FIELDS * sizeof(double),
+    MCD_HIP(c, hipMemcpyAsync(geom, c->g_geom, nc * MCD_GEOM_FIELDS * sizeof(double),
                               hipMemcpyDeviceToDevice, c->stream));
   if (gas)
-    MCD_HIP(c, hipMemcpyAsync(gas, c->d_gas, nc * MCD_GAS_FIELDS * sizeof(double),
+    MCD_HIP(c, hipMemcpyAsync(gas, c->gas, nc * MCD_GAS_FIELDS * sizeof(double),
                               hipMemcpyDeviceToDevice, c->stream));
   MCD_HIP(c, hipStreamSynchronize(c->stream));
   return MCD_OK;
@@ -889,17 +963,9 @@ const char *mcd_last_error(const mcd_ctx *c) {
 
 void mcd_free(mcd_ctx *c) {
   if (!c) return;
-  if (c->stream || c->d_state) (void)hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->stream);
   drop_graph(c);
-  free_grid(c);
-  BinBuffers &b = c->bb;
-  free_binning(b);
-  dfree(c->d_edges);
   dfree(c->d_grid);
-  dfree(c->d_mbak);
-  dfree(c->d_cbak);
-  dfree(c->d_sbak);
-  dfree(c->d_state);
   if (c->copy_stream) (void)hipStreamSynchronize(c->copy_stream);
   for (int k = 0; k < 2; ++k) {
     dfree(c->d_stage[k]);

@@ -958,7 +958,10 @@ __global__ __launch_bounds__(256, sizeof(RT) == 4 ? 3 : 2) void collide_batched(
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const uint32_t step = A.state->step;
   const size_t small_bytes = region_bytes<RT>(A.small_cap, 1);
-  int nw = A.n_big > 0 ? 4 : 1;
+  // list lengths from the device plan (zero for a grid that failed validation)
+  const int n_big = __builtin_amdgcn_readfirstlane(A.plan->n_big);
+  const int n_small = __builtin_amdgcn_readfirstlane(A.plan->n_small);
+  int nw = n_big > 0 ? 4 : 1;
   for (;;) {
     int cell = -1;
     if (nw == 4) {
@@ -966,7 +969,7 @@ __global__ __launch_bounds__(256, sizeof(RT) == 4 ? 3 : 2) void collide_batched(
       __syncthreads();
       const int item = s_item;
       __syncthreads();
-      if (item < A.n_big)
+      if (item < n_big)
         cell = A.big_list[item];
       else
         nw = 1;
@@ -975,7 +978,7 @@ __global__ __launch_bounds__(256, sizeof(RT) == 4 ? 3 : 2) void collide_batched(
       int item = 0;
       if (lane == 0) item = atomicAdd(&A.state->small_head, 1);
       item = readlane_i(item, 0);
-      if (item >= A.n_small) break;
+      if (item >= n_small) break;
       cell = A.small_list[item];
     }
     char *base = nw == 4 ? smem : smem + (size_t)wave * small_bytes;
@@ -988,6 +991,7 @@ __global__ __launch_bounds__(256, sizeof(RT) == 4 ? 3 : 2) void collide_batched(
 template <typename RT, int KMAX, bool FAST, bool PROB>
 __global__ __launch_bounds__(256) void collide_plain(CollideArgs A) {
   extern __shared__ __align__(16) char smem[];
+  if (A.plan->bad) return;  // an explicit grid that failed validation
   process_cell<RT, KMAX, FAST, PROB>(A, blockIdx.x, smem, A.big_cap, 4,
                                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
                                      threadIdx.x & 63, A.state->step);
@@ -1005,6 +1009,7 @@ __global__ void reset_queues(DevState *st) {
 template <typename RT, bool FAST>
 __global__ __launch_bounds__(256) void rates_cell(CollideArgs A, int cell, double *r_out,
                                                   int64_t ld, double *rowsum) {
+  if (A.plan->bad) return;
   const int s0 = A.cell_start[cell];
   const int n = A.cell_start[cell + 1] - s0;
   Gas g;
@@ -1058,8 +1063,9 @@ static hipError_t run_batched(const CollideArgs &a, int grid_override, hipStream
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, 256, lds);
   if (e != hipSuccess) return e;
   if (per_cu < 1) return hipErrorInvalidConfiguration;
-  const int units = a.n_big + (a.n_small + 3) / 4;
-  int grid = std::min(per_cu * cus, std::max(units, 1));
+  // persistent workgroups: as many as fit (the list lengths are on the
+  // device; workgroups beyond the work exit at their first queue pop)
+  int grid = per_cu * cus;
   if (grid_override > 0) grid = grid_override;
   reset_queues<<<1, 1, 0, s>>>(a.state);
   kern<<<grid, 256, lds, s>>>(a);

@@ -26,6 +26,27 @@ enum : uint32_t {
   FLAG_BAD_MASS = 1u << 1,   // non-positive or non-finite mass produced
   FLAG_BAD_VOLUME = 1u << 2, // non-positive cell volume with members
   FLAG_CAPACITY = 1u << 3,   // cell larger than the launch's capacity
+  FLAG_BAD_GRID = 1u << 4,   // explicit grid failed validation (nothing collides)
+};
+
+// largest cell any schedule takes, and the buckets of the size histogram
+constexpr int kMaxCell = 2048;
+constexpr int kPlanBuckets = kMaxCell + 1;
+
+// the cell lists of the batched launch, written by the planning kernels
+struct Plan {
+  int32_t n_big, n_small;      // list lengths
+  int32_t max_big, max_small;  // largest cell of each list
+  int32_t max_cell;            // largest cell of the grid
+  int32_t n_members;           // members of the grid
+  int32_t bad;                 // nonzero: the grid failed validation (empty lists)
+  int32_t pad;
+};
+
+struct PlanBuffers {
+  Plan *plan;
+  int32_t *big, *small;        // [cells] each
+  uint32_t *hist, *cursor;     // [kPlanBuckets] each
 };
 
 struct CollideArgs {
@@ -35,7 +56,7 @@ struct CollideArgs {
   const double *gas;        // [n_cells][6]
   const int32_t *big_list;  // cells processed by four-wave teams, largest first
   const int32_t *small_list;// cells processed by single waves, largest first
-  int32_t n_big, n_small;
+  const Plan *plan;         // list lengths (device), grid verdict
   int32_t big_cap, small_cap;   // particle capacity of a team's LDS region
   double *m;
   const double *M;
@@ -90,6 +111,26 @@ template <typename RT>
 constexpr size_t region_bytes(int cap, int waves) {
   return xbuf_offset<RT>(cap) + (sizeof(RT) == 4 && waves == 4 ? kXbufBytes : 0);
 }
+
+// largest FP64 cell: a four-wave team's region of 96-byte records and its
+// scratch must fit the 160 KB of LDS (the FP32 form's 48-byte records fit
+// kMaxCell)
+constexpr int kMaxCellFp64 = 1536;
+static_assert(region_bytes<double>(kMaxCellFp64, 4) <= 160 * 1024, "FP64 cells of kMaxCellFp64 fit");
+static_assert(region_bytes<double>(kMaxCellFp64 + 256, 4) > 160 * 1024, "and no larger ones");
+static_assert(region_bytes<float>(kMaxCell, 4) <= 160 * 1024, "FP32 cells of kMaxCell fit");
+
+// zero the device state and the plan of a new context
+hipError_t launch_clear_state(DevState *state, Plan *plan, hipStream_t s);
+
+// planning of the batched lists (plan.hip): an explicit grid is validated
+// (member ranges, cells of at most `bound` particles, member indices below
+// N) and its cells sorted by size; a uniform grid takes every cell in order
+hipError_t launch_plan_explicit(const int32_t *cell_start, const int32_t *order, int32_t nc,
+                                int64_t N, int32_t bound, int32_t small_max, PlanBuffers pb,
+                                DevState *state, hipStream_t s);
+hipError_t launch_plan_uniform(int32_t nc, int32_t size, int32_t small_max, PlanBuffers pb,
+                               hipStream_t s);
 
 // launchers (collide.hip)
 hipError_t launch_collide(const CollideArgs &a, int precision, int schedule, int n_cells,

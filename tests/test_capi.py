@@ -1,6 +1,8 @@
 """The C-ABI library without a GPU: it loads, exports every function that
-include/mcd.h declares, its ctypes mirrors have the header's layout, and
-argument validation rejects bad input before any device call."""
+include/mcd.h declares, its ctypes mirrors have the header's layout, the
+workspace size follows the layout it documents, and argument validation
+(parameters, particles, the caller's workspace) rejects bad input before any
+device call."""
 import ctypes as C
 import os
 import re
@@ -57,13 +59,56 @@ def test_struct_layouts_match_header(tmp_path):
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
 
 
-def _init(params, n=10):
+FAKE = 0x1000   # never dereferenced: validation fails first
+
+
+def _init(params, n=10, ws=FAKE, ws_bytes=1 << 40):
     lib = _lib.load()
     p = _lib.make_params(params)
-    fake = 0x1000   # never dereferenced: validation fails first
-    parts = _lib.Particles(n, fake, fake, fake, fake, fake, None)
+    parts = _lib.Particles(n, FAKE, FAKE, FAKE, FAKE, FAKE, None)
     ctx = C.c_void_p()
-    return lib.mcd_init(C.byref(p), C.byref(parts), None, C.byref(ctx)), ctx
+    return lib.mcd_init(C.byref(p), C.byref(parts), None, ws, ws_bytes, C.byref(ctx)), ctx
+
+
+def _ws_size(params, n, precision="mixed", max_cells=0):
+    lib = _lib.load()
+    p = _lib.make_params(params, precision, "batched", max_cells)
+    b = C.c_size_t()
+    st = lib.mcd_workspace_size(C.byref(p), n, C.byref(b))
+    return st, b.value
+
+
+def test_workspace_size_follows_its_layout():
+    P = W.benchmark_params(n_r=50, n_z=2)     # zones of 2000 and 4000 particles
+    st, b1 = _ws_size(P, 100_000)
+    assert st == _lib.MCD_OK
+    st, b2 = _ws_size(P, 200_000)
+    # per particle: grid order 4, binning 2 x (4 + 4) + 1 + 4, tuning backup 8 (+ 256-byte
+    # rounding and the radix histogram): about 34 bytes more per particle
+    assert 30 * 100_000 < b2 - b1 < 40 * 100_000, b2 - b1
+    # composition fractions add their tuning backup, 4 bytes per fraction and particle
+    _, b3 = _ws_size(W.benchmark_params(n_r=50, n_z=2, n_comp=8), 100_000)
+    assert abs((b3 - b1) - 32 * 100_000) <= 512
+    # explicit grids of more cells size the two cell lists (8 bytes per cell)
+    _, b4 = _ws_size(P, 100_000, max_cells=1_000_100)
+    assert abs((b4 - b1) - 8 * 1_000_000) <= 1024
+    # zones above 8192 particles need the global radix path's 20 bytes per particle
+    _, b5 = _ws_size(W.benchmark_params(n_r=2, n_z=50), 100_000)
+    _, b6 = _ws_size(W.benchmark_params(n_r=20, n_z=5), 100_000)
+    assert abs((b5 - b6) - 20 * 100_000) <= 4096
+    for bad in (0, -5, 1 << 31):
+        assert _ws_size(P, bad)[0] == _lib.MCD_EINVAL
+    assert _ws_size(W.benchmark_params(n_r=0), 100)[0] == _lib.MCD_EINVAL
+    assert _ws_size(P, 100, max_cells=-1)[0] == _lib.MCD_EINVAL
+
+
+def test_init_rejects_a_missing_or_small_workspace():
+    P = W.benchmark_params(n_r=2, n_z=2)
+    st, need = _ws_size(P, 10)
+    assert st == _lib.MCD_OK
+    assert _init(P, ws=None, ws_bytes=need)[0] == _lib.MCD_EINVAL
+    st, ctx = _init(P, ws_bytes=need - 1)
+    assert st == _lib.MCD_EINVAL and not ctx.value
 
 
 @pytest.mark.parametrize("bad", [
@@ -81,14 +126,15 @@ def test_init_rejects_bad_particles():
     lib = _lib.load()
     p = _lib.make_params(W.benchmark_params())
     ctx = C.c_void_p()
+    ws = (FAKE, 1 << 40)
     parts = _lib.Particles(0, 1, 1, 1, 1, 1, None)
-    assert lib.mcd_init(C.byref(p), C.byref(parts), None, C.byref(ctx)) == _lib.MCD_EINVAL
+    assert lib.mcd_init(C.byref(p), C.byref(parts), None, *ws, C.byref(ctx)) == _lib.MCD_EINVAL
     parts = _lib.Particles(10, 1, None, 1, 1, 1, None)
-    assert lib.mcd_init(C.byref(p), C.byref(parts), None, C.byref(ctx)) == _lib.MCD_EINVAL
+    assert lib.mcd_init(C.byref(p), C.byref(parts), None, *ws, C.byref(ctx)) == _lib.MCD_EINVAL
     p = _lib.make_params(W.benchmark_params(n_comp=8))
     parts = _lib.Particles(10, 1, 1, 1, 1, 1, None)
-    assert lib.mcd_init(C.byref(p), C.byref(parts), None, C.byref(ctx)) == _lib.MCD_EINVAL
-    assert lib.mcd_init(None, C.byref(parts), None, C.byref(ctx)) == _lib.MCD_EINVAL
+    assert lib.mcd_init(C.byref(p), C.byref(parts), None, *ws, C.byref(ctx)) == _lib.MCD_EINVAL
+    assert lib.mcd_init(None, C.byref(parts), None, *ws, C.byref(ctx)) == _lib.MCD_EINVAL
 
 
 def test_null_context_calls_are_rejected():
@@ -96,6 +142,8 @@ def test_null_context_calls_are_rejected():
     assert lib.mcd_bin(None, None) == _lib.MCD_EINVAL
     assert lib.mcd_step(None, 1.0, 0, 1) == _lib.MCD_EINVAL
     assert lib.mcd_rates(None, 0, None, 0, None) == _lib.MCD_EINVAL
+    assert lib.mcd_row_sums(None, None) == _lib.MCD_EINVAL
+    assert lib.mcd_workspace_size(None, 10, None) == _lib.MCD_EINVAL
     assert lib.mcd_get_stats(None, None) == _lib.MCD_EINVAL
     assert lib.mcd_last_error(None) == b"null context"
     assert lib.mcd_philox(None, 0, 0, None, -1, None) == _lib.MCD_EINVAL
