@@ -364,7 +364,33 @@ mcd_status mcd_set_event_log(mcd_ctx *ctx, int32_t *buf, int64_t per_cell);
 mcd_status mcd_philox(const uint32_t *ctr, uint32_t key_lo, uint32_t key_hi, uint32_t *out,
                       int64_t n, void *hip_stream);
 
-/* Human-readable description of the last error of ctx (never NULL). */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * collision step over explicit cells without a context or a workspace --
+ * what mcd_init, mcd_bin(cells) and mcd_step(dt, max_events, 1) do on a
+ * fresh context of the same params whose step counter is `step` (the
+ * Philox counter word of the step), with the same kernels and schedule.
+ * The device counters, the plan and the batched cell lists live in a
+ * library-internal device array of MCD_NOALLOC_SCRATCH_BYTES (about 8 MB),
+ * of which every GPU the library runs on holds one copy until the process
+ * ends; it is cleared by a kernel at every call.  Calls that overlap on one
+ * GPU (other streams, other host threads) race on it: serialise them.
+ * cells->max_cell must bound the cells (1..2048; grids are validated on the
+ * device as in mcd_bin, and a rejected grid collides nothing);
+ * cells->n_cells must be at most 2^20.  m (and comp) change in place.
+ * counts (device int64[6], may be NULL) receives the events, the outcome
+ * counts by MCD_OUT_* and the device anomaly flags of this call.  Async on
+ * hip_stream; allocates nothing and calls no allocating routine.
+ * MCD_EINVAL for bad params, particles, cells or limits (reason in
+ * mcd_last_error(NULL) on this thread). */
+#define MCD_NOALLOC_SCRATCH_BYTES 8406016
+mcd_status mcd_collide_noalloc(const mcd_params *params, const mcd_particles *particles,
+                               const mcd_cells *cells, double dt, int64_t max_events,
+                               uint32_t step, void *hip_stream, int64_t *counts);
+
+/* Human-readable description of the last error of ctx (never NULL); with
+ * ctx == NULL, of the last failed mcd_collide_noalloc on this thread, or
+ * "null context". */
 const char *mcd_last_error(const mcd_ctx *ctx);
 
 /* Release the workspace and the context (synchronises the stream first). */

@@ -29,7 +29,7 @@ GEOM_FIELDS = 5
 EXPORTS = ("mcd_workspace_size", "mcd_init", "mcd_bin", "mcd_rates", "mcd_row_sums", "mcd_step", "mcd_tune", "mcd_set_schedule",
            "mcd_set_gas_grid", "mcd_sigma_hist", "mcd_snapshot_bytes", "mcd_snapshot", "mcd_snapshot_wait",
            "mcd_get_stats", "mcd_get_cells", "mcd_set_event_log", "mcd_philox", "mcd_last_error",
-           "mcd_free")
+           "mcd_free", "mcd_collide_noalloc")
 
 
 class Params(C.Structure):
@@ -100,6 +100,8 @@ def load() -> C.CDLL:
         "mcd_set_event_log": (i32, [vp, vp, i64]),
         "mcd_philox": (i32, [vp, u32, u32, vp, i64, vp]),
         "mcd_last_error": (C.c_char_p, [vp]),
+        "mcd_collide_noalloc": (i32, [C.POINTER(Params), C.POINTER(Particles), C.POINTER(Cells),
+                                      C.c_double, i64, u32, vp, vp]),
         "mcd_free": (None, [vp]),
     }
     for name, (res, args) in sig.items():

@@ -242,6 +242,39 @@ class Snapshot:
         return out
 
 
+def collide_noalloc(params: dict, particles: dict, cells: dict, dt: float, max_events: int,
+                    step: int = 0, precision: str = "mixed", schedule: str = "batched",
+                    max_cell: int | None = None, counts: torch.Tensor | None = None,
+                    stream=None) -> torch.Tensor:
+    """One collision step over explicit cells through mcd_collide_noalloc
+    (no context, no workspace, no device allocation in the library); m and
+    comp change in place.  Returns the device int64 counts [events,
+    outcomes x4, flags] (`counts`, or a new tensor)."""
+    lib = _lib.load()
+    t = {k: _dev(particles[k], torch.float64, k) for k in ("m", "M")}
+    comp = particles.get("comp")
+    if comp is not None:
+        _dev(comp, torch.float32, "comp")
+    parts = _lib.Particles(t["m"].numel(), 0, 0, t["m"].data_ptr(), t["M"].data_ptr(), 0,
+                           comp.data_ptr() if comp is not None else None)
+    cs = _dev(cells["cell_start"], torch.int32, "cell_start")
+    order = _dev(cells["order"], torch.int32, "order")
+    gas = _dev(cells["gas"], torch.float64, "gas")
+    if max_cell is None:
+        max_cell = int(cells.get("max_cell", 0))
+    c = _lib.Cells(cs.numel() - 1, int(max_cell), cs.data_ptr(), order.data_ptr(), gas.data_ptr())
+    p = _lib.make_params(params, precision, schedule)
+    if counts is None:
+        counts = torch.zeros(6, dtype=torch.int64, device=t["m"].device)
+    _dev(counts, torch.int64, "counts")
+    st = lib.mcd_collide_noalloc(C.byref(p), C.byref(parts), C.byref(c), float(dt), int(max_events),
+                                 int(step) & 0xFFFFFFFF, _stream_handle(stream), counts.data_ptr())
+    if st != 0:
+        msg = lib.mcd_last_error(None)
+        raise MCDError(st, f"mcd_collide_noalloc: {msg.decode() if msg else ''}")
+    return counts
+
+
 def philox(ctr: torch.Tensor, key: int, stream=None) -> torch.Tensor:
     """Philox4x32-10 words on the device; ctr: int32 tensor [n, 4] (bit patterns)."""
     lib = _lib.load()

@@ -17,7 +17,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmcd.so")
-SOURCES = ["capi.hip", "collide.hip", "binning.hip", "plan.hip", "transport.hip", "diagnostics.hip"]
+SOURCES = ["capi.hip", "collide.hip", "binning.hip", "plan.hip", "transport.hip", "diagnostics.hip",
+           "noalloc.hip"]
 ARCH = os.environ.get("MCD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -19,7 +19,6 @@ using namespace mcd;
 namespace {
 
 constexpr int kSmallLimit = 512;      // largest single-wave cell a schedule may choose
-constexpr size_t kLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
 constexpr size_t kAlign = 256;        // alignment of every workspace array
 constexpr int64_t kMaxEdges = 1 << 16;  // histogram edges held in the workspace
 constexpr uint32_t kKnownFlags = DV_BROWNIAN | DV_TURB | DV_RADIAL | DV_AZIMUTHAL | DV_SETTLING |
@@ -174,6 +173,10 @@ void dfree(void *p) {
 
 bool pos_finite(double x) { return std::isfinite(x) && x > 0.0; }
 
+}  // namespace
+
+namespace mcd {
+
 std::string check_params(const mcd_params &p) {
   const struct {
     const char *name;
@@ -236,6 +239,10 @@ Model make_model(const mcd_params &p) {
   return m;
 }
 
+}  // namespace mcd
+
+namespace {
+
 void drop_graph(mcd_ctx *c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -285,16 +292,9 @@ mcd_status set_caps(mcd_ctx *c, int32_t max_big, int32_t max_small, int32_t max_
   c->max_big = max_big;
   c->max_small = max_small;
   c->max_cell = max_cell;
-  c->big_cap = max_big > 0 ? (max_big + 255) / 256 * 256 : 0;
-  c->small_cap = std::max(64, (max_small + 63) / 64 * 64);
-  // the plain schedule runs every cell on one four-wave workgroup
-  if (c->prm.schedule == MCD_SCHED_PLAIN) c->big_cap = std::max(256, (max_cell + 255) / 256 * 256);
   const bool f64 = c->prm.precision == MCD_FP64;
-  const size_t lds_big = f64 ? region_bytes<double>(c->big_cap, 4) : region_bytes<float>(c->big_cap, 4);
-  const size_t lds_small = 4 * (f64 ? region_bytes<double>(c->small_cap, 1)
-                                    : region_bytes<float>(c->small_cap, 1));
-  const size_t lds = c->prm.schedule == MCD_SCHED_PLAIN ? lds_big : std::max(lds_big, lds_small);
-  if (lds > kLdsBytes)
+  if (!lds_caps(c->prm.precision, c->prm.schedule, max_big, max_small, max_cell, c->big_cap,
+                c->small_cap))
     return fail(c, MCD_EINVAL,
                 std::string("largest cell does not fit the 160 KB LDS in this precision (") +
                     std::to_string(max_cell) + " particles; at most " +
@@ -427,7 +427,7 @@ mcd_status mcd_init(const mcd_params *params, const mcd_particles *particles, vo
   c->ws = (char *)(((uintptr_t)workspace + kAlign - 1) / kAlign * kAlign);
   carve(c);
   hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = launch_clear_state(c->d_state, c->pb.plan, c->stream);
+  if (e == hipSuccess) e = launch_clear_state(c->d_state, c->pb.plan, 0u, c->stream);
   int dev = 0;
   if (e == hipSuccess) e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -957,7 +957,7 @@ mcd_status mcd_philox(const uint32_t *ctr, uint32_t key_lo, uint32_t key_hi, uin
 }
 
 const char *mcd_last_error(const mcd_ctx *c) {
-  if (!c) return "null context";
+  if (!c) return mcd::contextless_error();
   return c->err.c_str();
 }
 

@@ -120,8 +120,42 @@ static_assert(region_bytes<double>(kMaxCellFp64, 4) <= 160 * 1024, "FP64 cells o
 static_assert(region_bytes<double>(kMaxCellFp64 + 256, 4) > 160 * 1024, "and no larger ones");
 static_assert(region_bytes<float>(kMaxCell, 4) <= 160 * 1024, "FP32 cells of kMaxCell fit");
 
-// zero the device state and the plan of a new context
-hipError_t launch_clear_state(DevState *state, Plan *plan, hipStream_t s);
+// zero the device state and the plan (a new context, or a context-free
+// step), with the Philox step index `step`
+hipError_t launch_clear_state(DevState *state, Plan *plan, uint32_t step, hipStream_t s);
+
+// LDS capacities of the collision launch from the largest cell of each list
+// (particles): false if a team's region does not fit the 160 KB of LDS
+inline bool lds_caps(int precision, int schedule, int max_big, int max_small, int max_cell,
+                     int &big_cap, int &small_cap) {
+  big_cap = max_big > 0 ? (max_big + 255) / 256 * 256 : 0;
+  small_cap = (max_small + 63) / 64 * 64;
+  if (small_cap < 64) small_cap = 64;
+  const int plain_cap = (max_cell + 255) / 256 * 256;
+  if (schedule == 0) big_cap = plain_cap > 256 ? plain_cap : 256;  // one team per cell
+  const bool f64 = precision == 0;
+  const size_t lds_big = f64 ? region_bytes<double>(big_cap, 4) : region_bytes<float>(big_cap, 4);
+  const size_t lds_small =
+      4 * (f64 ? region_bytes<double>(small_cap, 1) : region_bytes<float>(small_cap, 1));
+  const size_t lds = schedule == 0 ? lds_big : (lds_big > lds_small ? lds_big : lds_small);
+  return lds <= 160 * 1024;
+}
+
+}  // namespace mcd
+
+#include <string>
+
+#include "mcd.h"
+
+namespace mcd {
+
+// parameter checks ("" if valid) and the device model of a parameter set
+// (capi.hip), shared by the context and the context-free entry point
+std::string check_params(const mcd_params &p);
+Model make_model(const mcd_params &p);
+// message of the last failed context-free call on this thread
+// (noalloc.hip), or "null context"
+const char *contextless_error();
 
 // planning of the batched lists (plan.hip): an explicit grid is validated
 // (member ranges, cells of at most `bound` particles, member indices below

@@ -199,13 +199,15 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_uniform(int32_t nc, int32
   }
 }
 
-__global__ void k_clear_state(DevState *st, Plan *plan) {
-  *st = DevState{};
+__global__ void k_clear_state(DevState *st, Plan *plan, uint32_t step) {
+  DevState z{};
+  z.step = step;
+  *st = z;
   *plan = Plan{};
 }
 
-hipError_t launch_clear_state(DevState *state, Plan *plan, hipStream_t s) {
-  k_clear_state<<<1, 1, 0, s>>>(state, plan);
+hipError_t launch_clear_state(DevState *state, Plan *plan, uint32_t step, hipStream_t s) {
+  k_clear_state<<<1, 1, 0, s>>>(state, plan, step);
   return hipGetLastError();
 }
 
