@@ -181,18 +181,72 @@ def full_step(steps, warmup):
     b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    gpu_main = a.elapsed_time(b) / steps
     st = sim.stats()
-    sim.close()
     events = st["events"] - ev0
+    # a late window: the busiest cells' event chains grow with the disk's
+    # age, and with them the step (steps LATE_FROM .. LATE_FROM + LATE_STEPS - 1)
+    done = warmup + steps
+    if done < LATE_FROM:
+        sim.step(W.YR, 0, LATE_FROM - done)
+    ev1 = sim.stats()["events"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    a.record(stream)
+    sim.step(W.YR, 0, LATE_STEPS)   # graph replays, as in the main window
+    b.record(stream)
+    torch.cuda.synchronize()
+    wall_late = time.perf_counter() - t1
+    gpu_late = a.elapsed_time(b) / LATE_STEPS
+    late_events = sim.stats()["events"] - ev1
+    sim.close()
     n = len(work["particles"]["m"])
     return {"workload": "2-D disk 1-100 AU: 2e6 particles, 1000 x 10 equal-count cells of 200, "
                         "8 composition fractions, drift + settling + mixing + coagulation, "
                         "1 yr per step, time-limited events",
             "precision": "mixed", "schedule": "batched", "steps": steps, "warmup": warmup,
             "particles": n, "active": int(st["n_active"]),
-            "ms_per_step": wall / steps * 1e3, "gpu_ms_per_step": a.elapsed_time(b) / steps,
+            "ms_per_step": wall / steps * 1e3, "gpu_ms_per_step": gpu_main,
             "events_per_step": events / steps, "collisions_per_s": events / wall,
-            "bin_ms": bin_ms, "tuned_schedule": tuned}
+            "bin_ms": bin_ms, "tuned_schedule": tuned,
+            "late_window": {"from_step": max(LATE_FROM, done), "steps": LATE_STEPS,
+                            "ms_per_step": wall_late / LATE_STEPS * 1e3,
+                            "gpu_ms_per_step": gpu_late,
+                            "events_per_step": late_events / LATE_STEPS,
+                            "collisions_per_s": late_events / wall_late}}
+
+
+LATE_FROM, LATE_STEPS = 20, 20
+CLOCK_GHZ = 2.4
+
+
+def lone_cells():
+    """Latency of one cell's serial event chain: a single cell alone on the
+    GPU (mixed, batched schedule: one wave up to 256 particles, a four-wave
+    team above), 1000 events, HIP events around the launch after one
+    warm-up step; cycles at the 2.4 GHz peak clock."""
+    import numpy as np
+    import torch
+    from paper_2507_21239_amd import api
+    from paper_2507_21239_amd import workloads as W
+    out = {}
+    for n in (64, 200, 256, 1000):
+        work = W.c4_batched(seed=9, counts=[n], events=EVENTS_PER_CELL)
+        dev = api.to_device(work["particles"])
+        sim = api.Simulation(work["params"], dev, precision="mixed", schedule="batched")
+        sim.bin(api.cells_to_device(work["cells"]), max_cell=n)
+        sim.step(0.0, EVENTS_PER_CELL, 1)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        sim.step(0.0, EVENTS_PER_CELL, 1)
+        b.record()
+        torch.cuda.synchronize()
+        us = a.elapsed_time(b) * 1e3 / EVENTS_PER_CELL
+        sim.close()
+        out[str(n)] = {"waves": 1 if n <= 256 else 4, "us_per_event": us,
+                       "cycles_per_event": us * 1e-6 * CLOCK_GHZ * 1e9}
+    return out
 
 
 def next_rows(steps, warmup):
@@ -306,7 +360,7 @@ def configs_table(steps=10):
     from paper_2507_21239_amd import api
     from paper_2507_21239_amd import workloads as W
 
-    threads = os.cpu_count() or 1
+    threads = host_threads()
 
     def fresh(work):
         return {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in work["particles"].items()}
@@ -444,58 +498,181 @@ def error_report(work, n_sample=8):
     out["fp64_events_compared"] = len(pick) * EVENTS_PER_CELL
     out["fp64_mass_max_rel_err"] = mrel
     from scipy import stats as sst
+    # paired: the same cells on the same Philox stream, so the two forms mostly
+    # take the same events; a distance, not a test (the ensembles below are)
     ks = sst.ks_2samp(np.concatenate(om_all), np.concatenate(gm_all))
-    out["mixed_vs_oracle_logm_ks_D"] = float(ks.statistic)
-    out["mixed_vs_oracle_logm_ks_p"] = float(ks.pvalue)
-    out["ensemble"] = ensemble_report(work, pick)
+    out["mixed_vs_oracle_same_stream_logm_ks_D"] = float(ks.statistic)
     return out
 
 
-def ensemble_report(work, pick, seeds=8, steps=2):
-    """Mixed GPU form vs the FP64 oracle over Philox seeds: the sampled cells,
-    `steps` steps of 1000 events each; per seed the moment ratios M1/M0,
-    M2/M1, M3/M2 of the swarms (M_k = sum N_i m_i^k, N_i = M_i/m_i), then
-    their ensemble means, relative differences and standard errors, and a
-    KS test on the pooled log10 m."""
+def swarm_summary(m, M, active):
+    """Per-run summary of the active swarms (M_k = sum N_i m_i^k, N_i = M_i/m_i):
+    the moment ratios M1/M0, M2/M1, M3/M2, the mass-weighted mean log10 m and
+    the active count."""
+    import numpy as np
+    a = np.asarray(active).astype(bool)
+    m, M = np.asarray(m)[a], np.asarray(M)[a]
+    N = M / m
+    return {"M1/M0": M.sum() / N.sum(), "M2/M1": (M * m).sum() / M.sum(),
+            "M3/M2": (M * m * m).sum() / (M * m).sum(),
+            "mass-weighted mean log10 m": float((M * np.log10(m)).sum() / M.sum()),
+            "active": float(a.sum())}
+
+
+def compare_ensembles(a_runs, b_runs, a_name, b_name):
+    """Two ensembles of independent runs (disjoint seeds): per quantity the
+    means, standard errors over seeds and the difference in units of its
+    standard error (z); two-sample KS on the pooled log10 m of the
+    representative particles (they sample the mass distribution), with the
+    KS distance between the two halves of each ensemble as the reference for
+    sampling noise.  Tolerances: |z| <= 3 for every quantity, and the
+    cross-ensemble KS distance no larger than the larger half-vs-half one."""
     import numpy as np
     from scipy import stats as sst
+    out = {"runs": {a_name: len(a_runs), b_name: len(b_runs)}, "quantities": {}}
+    ok = True
+    for q in a_runs[0]["summary"]:
+        xa = np.array([r["summary"][q] for r in a_runs])
+        xb = np.array([r["summary"][q] for r in b_runs])
+        sa, sb = xa.std(ddof=1) / np.sqrt(len(xa)), xb.std(ddof=1) / np.sqrt(len(xb))
+        se = float(np.hypot(sa, sb))
+        z = float((xb.mean() - xa.mean()) / se) if se > 0 else (0.0 if xb.mean() == xa.mean() else float("inf"))
+        ok = ok and abs(z) <= 3.0
+        out["quantities"][q] = {a_name: float(xa.mean()), a_name + "_se": float(sa),
+                                b_name: float(xb.mean()), b_name + "_se": float(sb), "z": z}
+    la = [r["logm"] for r in a_runs]
+    lb = [r["logm"] for r in b_runs]
+    ks = sst.ks_2samp(np.concatenate(la), np.concatenate(lb))
+    h = lambda L: sst.ks_2samp(np.concatenate(L[: len(L) // 2]), np.concatenate(L[len(L) // 2:])).statistic
+    ref = max(float(h(la)), float(h(lb)))
+    out["logm_ks"] = {"D": float(ks.statistic), "p": float(ks.pvalue),
+                      "D_half_vs_half": ref, "samples": [int(sum(map(len, la))), int(sum(map(len, lb)))]}
+    ok = ok and float(ks.statistic) <= ref
+    out["within_tolerance"] = bool(ok)
+    return out
 
-    import oracle as O
+
+def _gpu_disk_run(work_fn, seed, precision, steps, tune=True):
+    import numpy as np
+    import torch
     from paper_2507_21239_amd import api
     from paper_2507_21239_amd import workloads as W
+    work = work_fn(seed)
+    dev = api.to_device(work["particles"])
+    sim = api.Simulation(work["params"], dev, precision=precision, schedule="batched")
+    sim.bin()
+    if tune:
+        choose_schedule(sim, W.YR, 0)
+    sim.step(W.YR, 0, steps)
+    ev = sim.stats()["events"]
+    torch.cuda.synchronize()
+    h = {k: dev[k].cpu().numpy() for k in ("m", "active")}
+    sim.close()
+    act = h["active"].astype(bool)
+    return {"summary": swarm_summary(h["m"], work["particles"]["M"], act),
+            "logm": np.log10(h["m"][act]), "events": int(ev)}
 
-    def ratios(m, M):
-        N = M / m
-        return [M.sum() / N.sum(), (M * m).sum() / M.sum(), (M * m * m).sum() / (M * m).sum()]
 
-    sub = W.subset_cells(work, np.array(pick))
-    ro, rg, lo, lg = [], [], [], []
-    for seed in range(seeds):
-        p = dict(sub["params"], seed=seed)
-        ref = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in sub["particles"].items()}
-        for s in range(steps):
-            O.collide_all(p, sub["cells"], s, ref, 0.0, EVENTS_PER_CELL, threads=os.cpu_count() or 1)
-        dev = api.to_device(sub["particles"])
-        sim = api.Simulation(p, dev, precision="mixed", schedule="batched")
-        sim.bin(api.cells_to_device(sub["cells"]))
-        sim.step(0.0, EVENTS_PER_CELL, steps)
-        g = dev["m"].cpu().numpy()
-        sim.close()
-        ro.append(ratios(ref["m"], ref["M"]))
-        rg.append(ratios(g, sub["particles"]["M"]))
-        lo.append(np.log10(ref["m"]))
-        lg.append(np.log10(g))
-    ro, rg = np.array(ro), np.array(rg)
-    se = lambda x: float(x.std(ddof=1) / np.sqrt(len(x)))
-    out = {"seeds": seeds, "steps": steps, "cells": len(pick)}
-    for k, name in enumerate(("M1/M0", "M2/M1", "M3/M2")):
-        mo, mg = float(ro[:, k].mean()), float(rg[:, k].mean())
-        out[name] = {"oracle": mo, "mixed": mg, "rel_diff": (mg - mo) / mo,
-                     "rel_se": float(np.hypot(se(ro[:, k]), se(rg[:, k])) / mo)}
-    ks = sst.ks_2samp(np.concatenate(lo), np.concatenate(lg))
-    out["logm_ks_D"] = float(ks.statistic)
-    out["logm_ks_p"] = float(ks.pvalue)
+def _oracle_disk_run(work_fn, seed, steps):
+    import numpy as np
+    import oracle as O
+    work = work_fn(seed)
+    part = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in work["particles"].items()}
+    ev = 0
+    for s in range(steps):
+        ev += int(O.step(work["params"], part, s, work["dt"], 0,
+                         threads=host_threads())["stats"]["events"].sum())
+    act = part["active"].astype(bool)
+    return {"summary": swarm_summary(part["m"], part["M"], act), "logm": np.log10(part["m"][act]),
+            "events": ev}
+
+
+def ensemble_report(seeds=16, steps=40):
+    """The mixed GPU form against the FP64 oracle as independent ensembles:
+    the Benchmark table's disk with 1e5 particles in 50 x 10 cells (drift,
+    settling, mixing, coagulation, 1 yr per step), `steps` steps from the
+    same initial state; the oracle with Philox seeds 0..seeds-1, the mixed
+    form with seeds seeds..2 seeds-1.  The two ensembles share no random
+    numbers, so their difference is a distributional one."""
+    from paper_2507_21239_amd import workloads as W
+    fn = lambda seed: dict(W.c3_disk(seed=0), params=dict(W.c3_disk(seed=0)["params"], seed=seed))
+    t0 = time.perf_counter()
+    orc = [_oracle_disk_run(fn, s, steps) for s in range(seeds)]
+    t1 = time.perf_counter()
+    mix = [_gpu_disk_run(fn, seeds + s, "mixed", steps) for s in range(seeds)]
+    out = compare_ensembles(orc, mix, "oracle", "mixed")
+    out.update({"workload": "2-D disk 1-100 AU, 1e5 particles, 50 x 10 cells, 1 yr per step",
+                "horizon_yr": steps, "oracle_seeds": [0, seeds - 1],
+                "mixed_seeds": [seeds, 2 * seeds - 1], "oracle_s": t1 - t0,
+                "events_per_run": {"oracle": float(sum(r["events"] for r in orc) / seeds),
+                                   "mixed": float(sum(r["events"] for r in mix) / seeds)}})
     return out
+
+
+def large_disk_ensemble(seeds=16, years=1000, oracle_steps=3):
+    """The large disk (2e6 particles, 1000 x 10 cells, 8 composition
+    fractions) as 16-seed ensembles: the mixed form (seeds 16..31) against
+    GPU FP64 (seeds 0..15) over `years` steps of 1 yr -- GPU FP64 stands in
+    for the oracle at this size and horizon (it takes the oracle's event
+    decisions bit for bit on short horizons) -- and against the oracle
+    itself (seeds 0..15) over the first `oracle_steps` steps."""
+    from paper_2507_21239_amd import workloads as W
+    fn = lambda seed: dict(W.c5_large_disk(seed=0), params=dict(W.c5_large_disk(seed=0)["params"], seed=seed))
+    res = {"workload": "2-D disk 1-100 AU, 2e6 particles, 1000 x 10 cells of 200, 8 composition "
+                       "fractions, 1 yr per step"}
+    t0 = time.perf_counter()
+    log("ensemble: large disk, FP64 GPU seeds 0..", seeds - 1, years, "yr")
+    f64 = [_gpu_disk_run(fn, s, "fp64", years) for s in range(seeds)]
+    log("ensemble: large disk, mixed seeds", seeds, "..", 2 * seeds - 1)
+    mix = [_gpu_disk_run(fn, seeds + s, "mixed", years) for s in range(seeds)]
+    res["mixed_vs_gpu_fp64"] = dict(compare_ensembles(f64, mix, "fp64", "mixed"), horizon_yr=years,
+                                    gpu_s=time.perf_counter() - t0)
+    log("ensemble: large disk, oracle", oracle_steps, "steps")
+    t1 = time.perf_counter()
+    orc = [_oracle_disk_run(fn, s, oracle_steps) for s in range(seeds)]
+    t2 = time.perf_counter()
+    mix_s = [_gpu_disk_run(fn, seeds + s, "mixed", oracle_steps, tune=False) for s in range(seeds)]
+    res["mixed_vs_oracle"] = dict(compare_ensembles(orc, mix_s, "oracle", "mixed"),
+                                  horizon_yr=oracle_steps, oracle_s=t2 - t1)
+    return res
+
+
+HOST_THREADS_MAX = 16   # the host-CPU share of one GPU on the measurement boxes
+
+
+def host_threads():
+    """Threads for the CPU oracle: the CPUs this process may run on, at most
+    the host share of one GPU."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(n, HOST_THREADS_MAX))
+
+
+def cpu_info():
+    """Model, the logical CPUs this process may use, and how many distinct
+    physical cores (and threads per core) they are, from /proc/cpuinfo."""
+    allowed = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else set()
+    cores, cpu, phys, core = {}, None, None, None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f.read().split("\n\n"):
+                kv = dict(x.split(":", 1) for x in line.splitlines() if ":" in x)
+                kv = {k.strip(): v.strip() for k, v in kv.items()}
+                if "processor" not in kv:
+                    continue
+                cpu = int(kv["processor"])
+                if allowed and cpu not in allowed:
+                    continue
+                key = (kv.get("physical id", "0"), kv.get("core id", str(cpu)))
+                cores.setdefault(key, []).append(cpu)
+    except OSError:
+        pass
+    logical = sum(len(v) for v in cores.values())
+    return {"model": cpu_model(), "logical_cpus_allowed": logical or (os.cpu_count() or 1),
+            "physical_cores_allowed": len(cores) or None,
+            "threads_per_core": (max(len(v) for v in cores.values()) if cores else None)}
 
 
 def cpu_model():
@@ -518,7 +695,7 @@ def cpu_baseline(work, target_s=12.0, one_thread_s=3.0):
     import oracle as O
     from paper_2507_21239_amd import workloads as W
 
-    threads = os.cpu_count() or 1
+    threads = host_threads()
     rng = np.random.default_rng(7)
     sizes = np.diff(work["cells"]["cell_start"])
     n_cells = len(sizes)
@@ -544,10 +721,12 @@ def cpu_baseline(work, target_s=12.0, one_thread_s=3.0):
 
     used, evs, ncells, evals = run(threads, target_s, max(threads, 8))
     u1, e1, c1, p1 = run(1, one_thread_s, 2)
+    info = cpu_info()
     return dict(value=evs / used, unit="collisions/s", cores=threads, kind="oracle",
+                host=dict(info, threads_used=threads),
                 sample=f"{ncells} of {n_cells} cells of the same workload, {EVENTS_PER_CELL} events "
                        f"each ({evs} events), FP64, {used:.1f} s wall",
-                pair_evals_per_s=evals / used, cpu_model=cpu_model(),
+                pair_evals_per_s=evals / used,
                 one_thread={"collisions_per_s": e1 / u1, "pair_evals_per_s": p1 / u1,
                             "sample": f"{c1} cells, {e1} events, {u1:.1f} s"})
 
@@ -562,8 +741,11 @@ def main():
     ap.add_argument("--modes", default="all",
                     help="all | headline | none (only the full step, for profiling) | "
                          "next (cost of the NEXT rows) | configs (per-configuration rates, "
-                         "GPU forms and oracle)")
+                         "GPU forms and oracle) | ensemble (the large disk's 16-seed "
+                         "ensembles, mixed vs GPU FP64 and vs the oracle)")
     ap.add_argument("--no-full-step", action="store_true", help="skip the full-path measurement")
+    ap.add_argument("--years", type=int, default=1000,
+                    help="horizon of --modes ensemble (the large disk's 16-seed ensembles)")
     ap.add_argument("--schedule", default=None,
                     help="SMALL_MAX,GRID_PER_CU: fixed batched schedule instead of the autotuner "
                          "(profiling runs, so that no tuning trials enter the kernel statistics)")
@@ -601,6 +783,10 @@ def main():
         print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
                           "cpu_model": cpu_model(), "configs": configs_table(args.steps)}),
               flush=True)
+        return
+    if args.modes == "ensemble":
+        print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
+                          "large_disk_ensemble": large_disk_ensemble(years=args.years)}), flush=True)
         return
     if args.modes == "none":
         fs = full_step(args.steps, args.warmup)
@@ -653,10 +839,15 @@ def main():
         log("full step on the large disk")
         out["full_step"] = full_step(args.steps, args.warmup)
         log("full step", f"{out['full_step']['ms_per_step']:.3f} ms/step",
-            f"bin {out['full_step']['bin_ms']:.3f} ms")
+            f"bin {out['full_step']['bin_ms']:.3f} ms",
+            f"late {out['full_step']['late_window']['ms_per_step']:.3f} ms/step")
+        log("lone cells")
+        out["lone_cell"] = lone_cells()
     if not args.no_error:
         log("error report")
         out["error"] = error_report(work)
+        log("error report: ensembles of the 1e5 disk, oracle vs mixed")
+        out["error"]["ensemble"] = ensemble_report()
     if not args.no_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(work)
