@@ -542,18 +542,49 @@ __device__ inline int event_outcome(const CollideArgs &A, const TeamScratch *S, 
     fast = !(dvj < (RT)P.v_frag);
   }
   const int oc = outcome<sizeof(RT) == 8>(P, fast, mi, mj, u4, mnew);
-  if (writer) {
-    if ((!(mnew > 0.0) || !isfinite(mnew)) && lane == 0) atomicOr(&A.state->flags, FLAG_BAD_MASS);
-    if (A.comp != nullptr && P.n_comp > 0 && (oc == OUT_STICK || oc == OUT_FRAG) &&
-        lane < P.n_comp) {
-      const double wi = mi, wj = group_factor(P.dm_max, mi, mj) * mj;
-      float *cs = A.comp + (size_t)lane * A.N;
-      const double cI = (double)cs[gi], cJ = (double)cs[gj];
-      cs[gi] = (float)((wi * cI + wj * cJ) / (wi + wj));
-    }
-  }
+  if (writer && (!(mnew > 0.0) || !isfinite(mnew)) && lane == 0)
+    atomicOr(&A.state->flags, FLAG_BAD_MASS);
   rin = RecAfter<RT>::get(A.P, S, mnew, Mi, Mn);
   return oc;
+}
+
+// Composition of i after a sticking or fragmenting event: mass-weighted mix
+// of i's fractions (weight m_i) and j's (weight g m_j), one component per
+// lane below n_comp.  The fractions are loaded as soon as i and j are known
+// (comp_load) and the mix is stored once the event is done (comp_store), so
+// that the memory latency overlaps the event's rate updates instead of
+// stalling its chain; a later event of the same lane reads its own store.
+struct CompMix {
+  float cI, cJ;
+  bool on;
+};
+__device__ inline CompMix comp_load(const CollideArgs &A, int lane, bool writer, int gi, int gj) {
+  CompMix c{0.0f, 0.0f, false};
+  if (writer && A.comp != nullptr && lane < A.P.n_comp) {
+    // the component's base is formed here, per event, not held (or spilled)
+    // across the event loop
+    const float *cs = A.comp + (size_t)opaque_v(lane) * A.N;
+    c.cI = cs[gi];
+    c.cJ = cs[gj];
+    c.on = true;
+  }
+  return c;
+}
+template <bool EXACT>
+__device__ inline void comp_store(const CollideArgs &A, const CompMix &c, int lane, int oc, int gi,
+                                  double mi, double mj) {
+  if (c.on && (oc == OUT_STICK || oc == OUT_FRAG)) {
+    // the grouped mass g m_j as the outcome formed it
+    double wj;
+    if (EXACT) {
+      wj = group_factor(A.P.dm_max, mi, mj) * mj;
+    } else {
+      const double d = A.P.dm_max * mi;
+      wj = (A.P.dm_max > 0.0 && d > mj) ? d : mj;
+    }
+    A.comp[(size_t)opaque_v(lane) * A.N + gi] =
+        (float)((mi * (double)c.cI + wj * (double)c.cJ) / (mi + wj));
+  }
 }
 
 __device__ inline void log_event(const CollideArgs &A, int cell, uint32_t e, int i_local,
@@ -567,11 +598,12 @@ __device__ inline void log_event(const CollideArgs &A, int cell, uint32_t e, int
   }
 }
 
-template <typename RT, int KMAX, bool FAST, bool PROB>
-__device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap, int nw, int wave,
+template <typename RT, int KMAX, bool FAST, bool PROB, int NW>
+__device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap, int wave,
                              int lane, uint32_t step) {
-  const int s0 = A.cell_start[cell];
-  const int n = A.cell_start[cell + 1] - s0;
+  constexpr int nw = NW;  // waves of the team: 1, or 4 (a compile-time shape per cell body)
+  const int s0 = __builtin_amdgcn_readfirstlane(A.cell_start[cell]);
+  const int n = __builtin_amdgcn_readfirstlane(A.cell_start[cell + 1]) - s0;
   if (n <= 0) return;
   const int TL = 64 * nw;
   const int K = (n + TL - 1) / TL;
@@ -593,8 +625,8 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     // grid sizes opaque per cell: the node lookups' bounds are formed here
     // instead of being held through every cell of a persistent launch
     Model Pl = A.P;
-    Pl.grid.nr = opaque_s(Pl.grid.nr);
-    Pl.grid.nz = opaque_s(Pl.grid.nz);
+    Pl.grid.nr = opaque_u(Pl.grid.nr);
+    Pl.grid.nz = opaque_u(Pl.grid.nz);
     gas_from_primaries(Pl, A.gas + (size_t)cell * 6, g);
   }
   if (!(g.V > 0.0)) {
@@ -773,7 +805,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
       e0 = e;
       const uint32_t ec = (uint32_t)(e + lane);
       // the key schedule is formed here, once per 64 events, not held
-      const uint32_t k0 = opaque_s(A.P.key0), k1 = opaque_s(A.P.key1);
+      const uint32_t k0 = opaque_u(A.P.key0), k1 = opaque_u(A.P.key1);
       const U4 w0 = philox4x32_10(U4{ec, c32, step, 0u}, k0, k1);
       const U4 w1 = philox4x32_10(U4{ec, c32, step, 1u}, k0, k1);
       if (timed) nlu1 = -log(u01(w0.x, w0.y));
@@ -873,6 +905,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     // (only i changes), computed alike by every wave; wave 0 writes
     const Cand cj = team_pick<KMAX>(tm, incl1, part1, rij, K, readlane_d(uu3, rl) * Ri, nw, 0.0,
                                     m64, dvv, gix);
+    const CompMix cm = comp_load(A, lane, wave == 0, gi, cj.gi);
     double mnew = 0.0;
     Rec<RT> rin;
     const int oc = event_outcome<RT, PROB>(A, tm.S, mi, cj.p0, Mi, ri.Mn, (RT)cj.p1,
@@ -928,6 +961,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
       for (int q = 0; q < KMAX; ++q)
         if (q == ci.q) r[q] = ri_new;
     }
+    comp_store<sizeof(RT) == 8>(A, cm, lane, oc, gi, mi, cj.p0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) oc_count[k] += (oc == k) ? 1u : 0u;
     ++e;
@@ -967,10 +1001,10 @@ __global__ __launch_bounds__(256, sizeof(RT) == 4 ? 3 : 2) void collide_batched(
     if (nw == 4) {
       if (threadIdx.x == 0) s_item = atomicAdd(&A.state->big_head, 1);
       __syncthreads();
-      const int item = s_item;
+      const int item = __builtin_amdgcn_readfirstlane(s_item);
       __syncthreads();
       if (item < n_big)
-        cell = A.big_list[item];
+        cell = __builtin_amdgcn_readfirstlane(A.big_list[item]);
       else
         nw = 1;
     }
@@ -979,11 +1013,13 @@ __global__ __launch_bounds__(256, sizeof(RT) == 4 ? 3 : 2) void collide_batched(
       if (lane == 0) item = atomicAdd(&A.state->small_head, 1);
       item = readlane_i(item, 0);
       if (item >= n_small) break;
-      cell = A.small_list[item];
+      cell = __builtin_amdgcn_readfirstlane(A.small_list[item]);
     }
-    char *base = nw == 4 ? smem : smem + (size_t)wave * small_bytes;
-    process_cell<RT, KMAX, FAST, PROB>(A, cell, base, nw == 4 ? A.big_cap : A.small_cap, nw,
-                                 nw == 4 ? wave : 0, lane, step);
+    if (nw == 4)
+      process_cell<RT, KMAX, FAST, PROB, 4>(A, cell, smem, A.big_cap, wave, lane, step);
+    else
+      process_cell<RT, KMAX, FAST, PROB, 1>(A, cell, smem + (size_t)wave * small_bytes, A.small_cap,
+                                            0, lane, step);
   }
 }
 
@@ -992,9 +1028,9 @@ template <typename RT, int KMAX, bool FAST, bool PROB>
 __global__ __launch_bounds__(256) void collide_plain(CollideArgs A) {
   extern __shared__ __align__(16) char smem[];
   if (A.plan->bad) return;  // an explicit grid that failed validation
-  process_cell<RT, KMAX, FAST, PROB>(A, blockIdx.x, smem, A.big_cap, 4,
-                                     __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
-                                     threadIdx.x & 63, A.state->step);
+  process_cell<RT, KMAX, FAST, PROB, 4>(A, blockIdx.x, smem, A.big_cap,
+                                        __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
+                                        threadIdx.x & 63, A.state->step);
 }
 
 __global__ void reset_queues(DevState *st) {

@@ -88,6 +88,16 @@ __device__ inline T opaque_s(T x) {
   asm volatile("" : "+s"(x));
   return x;
 }
+// opaque_s for a value that may be held in a vector register at the point of
+// use (uniform, but not provably so to the compiler): through a VGPR, then
+// the first lane
+template <typename T>
+__device__ inline T opaque_u(T x) {
+  static_assert(sizeof(T) == 4, "32-bit values");
+  int v = __builtin_bit_cast(int, x);
+  asm volatile("" : "+v"(v));
+  return __builtin_bit_cast(T, __builtin_amdgcn_readfirstlane(v));
+}
 // the same for a per-lane 32-bit value (kept in a vector register)
 template <typename T>
 __device__ inline T opaque_v(T x) {
