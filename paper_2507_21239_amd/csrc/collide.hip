@@ -433,7 +433,7 @@ __device__ inline bool wave_pick(int wave, double incl, double part, const VT *v
   c.q = qs;
   c.lane = wave * 64 + src;
   c.hit = first >= 0 ? 1 : 0;
-  c.p0 = c.p1 = c.p2 = 0.0;
+  c.p0 = c.p1 = 0.0;
   c.gi = -1;
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) {
@@ -474,7 +474,7 @@ template <int KMAX, typename VT, typename PT>
 __device__ inline Cand pick_all_waves(Team &tm, double incl, double part, const VT *v, int K,
                                       double target, const double *a0, const PT *a1,
                                       const int *ai) {
-  Cand h{0.0, 0.0, 0.0, -1, -1, 0, -1};
+  Cand h{0.0, 0.0, -1, -1, 0, -1};
   if (!wave_pick<KMAX>(tm.wave, incl, part, v, K, target, a0, a1, ai, h)) h.q = -1;
   tm.phase ^= 1;
   if (tm.lane == 0) tm.S->cand[tm.phase][tm.wave] = h;
@@ -488,7 +488,7 @@ __device__ inline Cand pick_all_waves(Team &tm, double incl, double part, const 
     for (int w = 0; w < tm.nw; ++w)
       if (tm.S->cand[tm.phase][w].q >= 0) wsel = w;
   }
-  if (wsel < 0) return Cand{0.0, 0.0, 0.0, -1, -1, 0, -1};
+  if (wsel < 0) return Cand{0.0, 0.0, -1, -1, 0, -1};
   return tm.S->cand[tm.phase][wsel];
 }
 
@@ -499,7 +499,7 @@ template <int KMAX, typename VT, typename PT>
 __device__ inline Cand team_pick(Team &tm, double incl, double part, const VT *v, int K,
                                  double target, int fix_wave, double delta, const double *a0,
                                  const PT *a1, const int *ai) {
-  Cand c{0.0, 0.0, 0.0, -1, -1, 0, -1};
+  Cand c{0.0, 0.0, -1, -1, 0, -1};
   if (tm.nw == 1) {
     if (!wave_pick<KMAX>(0, incl, part, v, K, target, a0, a1, ai, c)) c.q = -1;
     return c;

@@ -72,7 +72,7 @@ struct CollideArgs {
 
 // a selection result: payloads of the chosen slot, its slot and team lane
 struct Cand {
-  double p0, p1, p2;
+  double p0, p1;
   int q, lane, hit, gi;
 };
 
