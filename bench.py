@@ -622,14 +622,23 @@ def large_disk_ensemble(seeds=16, years=1000, oracle_steps=3):
                        "fractions, 1 yr per step"}
     t0 = time.perf_counter()
     log("ensemble: large disk, FP64 GPU seeds 0..", seeds - 1, years, "yr")
-    f64 = [_gpu_disk_run(fn, s, "fp64", years) for s in range(seeds)]
-    log("ensemble: large disk, mixed seeds", seeds, "..", 2 * seeds - 1)
-    mix = [_gpu_disk_run(fn, seeds + s, "mixed", years) for s in range(seeds)]
+    f64, mix = [], []
+    for s in range(seeds):
+        f64.append(_gpu_disk_run(fn, s, "fp64", years))
+        log("ensemble: fp64 seed", s, "done,", f"{time.perf_counter() - t0:.1f} s")
+    t_mid = time.perf_counter()
+    for s in range(seeds):
+        mix.append(_gpu_disk_run(fn, seeds + s, "mixed", years))
+        log("ensemble: mixed seed", seeds + s, "done,", f"{time.perf_counter() - t0:.1f} s")
     res["mixed_vs_gpu_fp64"] = dict(compare_ensembles(f64, mix, "fp64", "mixed"), horizon_yr=years,
-                                    gpu_s=time.perf_counter() - t0)
+                                    fp64_s_per_run=(t_mid - t0) / seeds,
+                                    mixed_s_per_run=(time.perf_counter() - t_mid) / seeds)
     log("ensemble: large disk, oracle", oracle_steps, "steps")
     t1 = time.perf_counter()
-    orc = [_oracle_disk_run(fn, s, oracle_steps) for s in range(seeds)]
+    orc = []
+    for s in range(seeds):
+        orc.append(_oracle_disk_run(fn, s, oracle_steps))
+        log("ensemble: oracle seed", s, "done,", f"{time.perf_counter() - t1:.1f} s")
     t2 = time.perf_counter()
     mix_s = [_gpu_disk_run(fn, seeds + s, "mixed", oracle_steps, tune=False) for s in range(seeds)]
     res["mixed_vs_oracle"] = dict(compare_ensembles(orc, mix_s, "oracle", "mixed"),
