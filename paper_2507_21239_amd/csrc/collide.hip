@@ -551,9 +551,11 @@ __device__ inline int event_outcome(const CollideArgs &A, const TeamScratch *S, 
 // Composition of i after a sticking or fragmenting event: mass-weighted mix
 // of i's fractions (weight m_i) and j's (weight g m_j), one component per
 // lane below n_comp.  The fractions are loaded as soon as i and j are known
-// (comp_load) and the mix is stored once the event is done (comp_store), so
-// that the memory latency overlaps the event's rate updates instead of
-// stalling its chain; a later event of the same lane reads its own store.
+// (comp_load) and the mix is stored early in the next event, once its i is
+// chosen, or when the cell ends (comp_store): the loads then have the rest of
+// the event and the next event's selection of i to arrive instead of
+// stalling the chain.  The next event's own loads come after that store, and
+// a load of a lane after its own store to the same address reads the store.
 struct CompMix {
   float cI, cJ;
   bool on;
@@ -598,7 +600,8 @@ __device__ inline void log_event(const CollideArgs &A, int cell, uint32_t e, int
   }
 }
 
-template <typename RT, int KMAX, bool FAST, bool PROB, int NW>
+// COMP: the composition mix is compiled in (a launch with fractions to track)
+template <typename RT, int KMAX, bool FAST, bool PROB, bool COMP, int NW>
 __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap, int wave,
                              int lane, uint32_t step) {
   constexpr int nw = NW;  // waves of the team: 1, or 4 (a compile-time shape per cell body)
@@ -773,6 +776,10 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
   // event e0 + l from Philox(e0 + l, cell, step, 0) and (.., 1)
   double nlu1 = 0.0, uu2 = 0.0, uu3 = 0.0, uu4 = 0.0, uu5 = 0.0;
   uint32_t e0 = 0u - 64u;  // first event of the current batch (none yet)
+  // the previous event's composition mix, not yet stored
+  CompMix pcm{0.0f, 0.0f, false};
+  int p_oc = 0, p_gi = 0;
+  double p_mi = 0.0, p_mj = 0.0;
   const int K_cell = K, lane_cell = lane, wave_cell = wave;
   for (;;) {
     // K and the lane / wave indices per event: tests such as q < K, w < wave
@@ -855,6 +862,12 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
       if (tl == 0) atomicOr(&A.state->flags, FLAG_BAD_RATE);
       break;
     }
+    if constexpr (COMP) {
+      if (pcm.on) {
+        comp_store<sizeof(RT) == 8>(A, pcm, lane, p_oc, p_gi, p_mi, p_mj);
+        pcm.on = false;
+      }
+    }
     t = t_next;
     const int si = ci.q * TL + ci.lane;
     const int i_local = ci.lane * K + ci.q;
@@ -905,7 +918,8 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     // (only i changes), computed alike by every wave; wave 0 writes
     const Cand cj = team_pick<KMAX>(tm, incl1, part1, rij, K, readlane_d(uu3, rl) * Ri, nw, 0.0,
                                     m64, dvv, gix);
-    const CompMix cm = comp_load(A, lane, wave == 0, gi, cj.gi);
+    CompMix cm{0.0f, 0.0f, false};
+    if constexpr (COMP) cm = comp_load(A, lane, wave == 0, gi, cj.gi);
     double mnew = 0.0;
     Rec<RT> rin;
     const int oc = event_outcome<RT, PROB>(A, tm.S, mi, cj.p0, Mi, ri.Mn, (RT)cj.p1,
@@ -961,10 +975,19 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
       for (int q = 0; q < KMAX; ++q)
         if (q == ci.q) r[q] = ri_new;
     }
-    comp_store<sizeof(RT) == 8>(A, cm, lane, oc, gi, mi, cj.p0);
+    if constexpr (COMP) {
+      pcm = cm;
+      p_oc = oc;
+      p_gi = gi;
+      p_mi = mi;
+      p_mj = cj.p0;
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) oc_count[k] += (oc == k) ? 1u : 0u;
     ++e;
+  }
+  if constexpr (COMP) {
+    if (pcm.on) comp_store<sizeof(RT) == 8>(A, pcm, lane, p_oc, p_gi, p_mi, p_mj);
   }
   // masses back to HBM
 #pragma unroll
@@ -985,7 +1008,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
 // on four-wave teams (largest first), then small cells on single waves
 // (largest first), each wave popping its own work
 // ---------------------------------------------------------------------------
-template <typename RT, int KMAX, bool FAST, bool PROB>
+template <typename RT, int KMAX, bool FAST, bool PROB, bool COMP>
 __global__ __launch_bounds__(256, sizeof(RT) == 4 ? 3 : 2) void collide_batched(CollideArgs A) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_item;
@@ -1016,9 +1039,10 @@ __global__ __launch_bounds__(256, sizeof(RT) == 4 ? 3 : 2) void collide_batched(
       cell = __builtin_amdgcn_readfirstlane(A.small_list[item]);
     }
     if (nw == 4)
-      process_cell<RT, KMAX, FAST, PROB, 4>(A, cell, smem, A.big_cap, wave, lane, step);
+      process_cell<RT, KMAX, FAST, PROB, COMP, 4>(A, cell, smem, A.big_cap, wave, lane, step);
     else
-      process_cell<RT, KMAX, FAST, PROB, 1>(A, cell, smem + (size_t)wave * small_bytes, A.small_cap,
+      process_cell<RT, KMAX, FAST, PROB, COMP, 1>(A, cell, smem + (size_t)wave * small_bytes,
+                                                  A.small_cap,
                                             0, lane, step);
   }
 }
@@ -1028,9 +1052,10 @@ template <typename RT, int KMAX, bool FAST, bool PROB>
 __global__ __launch_bounds__(256) void collide_plain(CollideArgs A) {
   extern __shared__ __align__(16) char smem[];
   if (A.plan->bad) return;  // an explicit grid that failed validation
-  process_cell<RT, KMAX, FAST, PROB, 4>(A, blockIdx.x, smem, A.big_cap,
-                                        __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
-                                        threadIdx.x & 63, A.state->step);
+  // the composition mix is compiled in; it applies when fractions are given
+  process_cell<RT, KMAX, FAST, PROB, true, 4>(A, blockIdx.x, smem, A.big_cap,
+                                              __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
+                                              threadIdx.x & 63, A.state->step);
 }
 
 __global__ void reset_queues(DevState *st) {
@@ -1090,7 +1115,10 @@ static hipError_t prepare(Kern kern, size_t lds) {
 template <typename RT, int KMAX, bool FAST, bool PROB>
 static hipError_t run_batched(const CollideArgs &a, int grid_override, hipStream_t s) {
   const size_t lds = std::max(region_bytes<RT>(a.big_cap, 4), 4 * region_bytes<RT>(a.small_cap, 1));
-  auto kern = collide_batched<RT, KMAX, FAST, PROB>;
+  // the composition mix only where there are fractions to track
+  const bool comp = a.comp != nullptr && a.P.n_comp > 0;
+  auto kern = comp ? collide_batched<RT, KMAX, FAST, PROB, true>
+                   : collide_batched<RT, KMAX, FAST, PROB, false>;
   hipError_t e = prepare(kern, lds);
   int dev = 0, cus = 0, per_cu = 0;
   if (e == hipSuccess) e = hipGetDevice(&dev);
