@@ -600,8 +600,10 @@ __device__ inline void log_event(const CollideArgs &A, int cell, uint32_t e, int
   }
 }
 
-// COMP: the composition mix is compiled in (a launch with fractions to track)
-template <typename RT, int KMAX, bool FAST, bool PROB, bool COMP, int NW>
+// AUX: the composition mix and the event log are compiled in (a launch with
+// fractions to track or events to record); without them the event loop
+// carries neither
+template <typename RT, int KMAX, bool FAST, bool PROB, bool AUX, int NW>
 __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap, int wave,
                              int lane, uint32_t step) {
   constexpr int nw = NW;  // waves of the team: 1, or 4 (a compile-time shape per cell body)
@@ -862,7 +864,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
       if (tl == 0) atomicOr(&A.state->flags, FLAG_BAD_RATE);
       break;
     }
-    if constexpr (COMP) {
+    if constexpr (AUX) {
       if (pcm.on) {
         comp_store<sizeof(RT) == 8>(A, pcm, lane, p_oc, p_gi, p_mi, p_mj);
         pcm.on = false;
@@ -902,7 +904,9 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
         for (int q = 0; q < KMAX; ++q)
           if (q == ci.q) r[q] = 0.0;
       }
-      if (tl == 0) log_event(A, cell, e, i_local, -1, -1);
+      if constexpr (AUX) {
+        if (tl == 0) log_event(A, cell, e, i_local, -1, -1);
+      }
       ++e;
       part = 0.0;
 #pragma unroll
@@ -919,14 +923,16 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     const Cand cj = team_pick<KMAX>(tm, incl1, part1, rij, K, readlane_d(uu3, rl) * Ri, nw, 0.0,
                                     m64, dvv, gix);
     CompMix cm{0.0f, 0.0f, false};
-    if constexpr (COMP) cm = comp_load(A, lane, wave == 0, gi, cj.gi);
+    if constexpr (AUX) cm = comp_load(A, lane, wave == 0, gi, cj.gi);
     double mnew = 0.0;
     Rec<RT> rin;
     const int oc = event_outcome<RT, PROB>(A, tm.S, mi, cj.p0, Mi, ri.Mn, (RT)cj.p1,
                                            readlane_d(uu4, rl),
                                            PROB ? readlane_d(uu5, rl) : 0.0, gi, cj.gi, lane,
                                            wave == 0, mnew, rin);
-    if (tl == 0) log_event(A, cell, e, i_local, cj.lane * K + cj.q, oc);
+    if constexpr (AUX) {
+      if (tl == 0) log_event(A, cell, e, i_local, cj.lane * K + cj.q, oc);
+    }
     // the owner of i keeps the new mass and record; it alone reads the slot
     // until the next exchange
     if (tl == ci.lane) {
@@ -975,7 +981,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
       for (int q = 0; q < KMAX; ++q)
         if (q == ci.q) r[q] = ri_new;
     }
-    if constexpr (COMP) {
+    if constexpr (AUX) {
       pcm = cm;
       p_oc = oc;
       p_gi = gi;
@@ -986,7 +992,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
     for (int k = 0; k < 4; ++k) oc_count[k] += (oc == k) ? 1u : 0u;
     ++e;
   }
-  if constexpr (COMP) {
+  if constexpr (AUX) {
     if (pcm.on) comp_store<sizeof(RT) == 8>(A, pcm, lane, p_oc, p_gi, p_mi, p_mj);
   }
   // masses back to HBM
@@ -1008,7 +1014,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
 // on four-wave teams (largest first), then small cells on single waves
 // (largest first), each wave popping its own work
 // ---------------------------------------------------------------------------
-template <typename RT, int KMAX, bool FAST, bool PROB, bool COMP>
+template <typename RT, int KMAX, bool FAST, bool PROB, bool AUX>
 __global__ __launch_bounds__(256, sizeof(RT) == 4 ? 3 : 2) void collide_batched(CollideArgs A) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_item;
@@ -1039,9 +1045,9 @@ __global__ __launch_bounds__(256, sizeof(RT) == 4 ? 3 : 2) void collide_batched(
       cell = __builtin_amdgcn_readfirstlane(A.small_list[item]);
     }
     if (nw == 4)
-      process_cell<RT, KMAX, FAST, PROB, COMP, 4>(A, cell, smem, A.big_cap, wave, lane, step);
+      process_cell<RT, KMAX, FAST, PROB, AUX, 4>(A, cell, smem, A.big_cap, wave, lane, step);
     else
-      process_cell<RT, KMAX, FAST, PROB, COMP, 1>(A, cell, smem + (size_t)wave * small_bytes,
+      process_cell<RT, KMAX, FAST, PROB, AUX, 1>(A, cell, smem + (size_t)wave * small_bytes,
                                                   A.small_cap,
                                             0, lane, step);
   }
@@ -1052,7 +1058,8 @@ template <typename RT, int KMAX, bool FAST, bool PROB>
 __global__ __launch_bounds__(256) void collide_plain(CollideArgs A) {
   extern __shared__ __align__(16) char smem[];
   if (A.plan->bad) return;  // an explicit grid that failed validation
-  // the composition mix is compiled in; it applies when fractions are given
+  // the composition mix and the event log are compiled in; they apply when
+  // fractions are given or a log is set
   process_cell<RT, KMAX, FAST, PROB, true, 4>(A, blockIdx.x, smem, A.big_cap,
                                               __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
                                               threadIdx.x & 63, A.state->step);
@@ -1115,10 +1122,10 @@ static hipError_t prepare(Kern kern, size_t lds) {
 template <typename RT, int KMAX, bool FAST, bool PROB>
 static hipError_t run_batched(const CollideArgs &a, int grid_override, hipStream_t s) {
   const size_t lds = std::max(region_bytes<RT>(a.big_cap, 4), 4 * region_bytes<RT>(a.small_cap, 1));
-  // the composition mix only where there are fractions to track
-  const bool comp = a.comp != nullptr && a.P.n_comp > 0;
-  auto kern = comp ? collide_batched<RT, KMAX, FAST, PROB, true>
-                   : collide_batched<RT, KMAX, FAST, PROB, false>;
+  // the composition mix and the event log only where they are used
+  const bool aux = (a.comp != nullptr && a.P.n_comp > 0) || a.evlog != nullptr;
+  auto kern = aux ? collide_batched<RT, KMAX, FAST, PROB, true>
+                  : collide_batched<RT, KMAX, FAST, PROB, false>;
   hipError_t e = prepare(kern, lds);
   int dev = 0, cus = 0, per_cu = 0;
   if (e == hipSuccess) e = hipGetDevice(&dev);
