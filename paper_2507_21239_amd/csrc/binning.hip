@@ -519,13 +519,22 @@ __global__ __launch_bounds__(1024) void k_zone_sort(const int32_t *__restrict__ 
   }
   if (shift > 0) {
     // runs of equal reduced keys, re-sorted by (full bits, index) by the
-    // thread that holds the run's first position
+    // thread that holds the run's first position.  Only members of such runs
+    // need their full bits (read again from z): a reduced key keeps 32
+    // significant bits of the zone's range, so runs are rare
     uint64_t *lz = lk + P;
     __syncthreads();
 #pragma unroll
+    for (int e = 0; e < kZoneItems; ++e) lk[base + e] = key[e];
+    __syncthreads();
+#pragma unroll
     for (int e = 0; e < kZoneItems; ++e) {
-      lk[base + e] = key[e];
-      lz[base + e] = base + e < nk ? key_bits(z[(int32_t)(uint32_t)key[e]]) : ~0ull;
+      const int p = base + e;
+      if (p >= nk) continue;
+      const uint32_t h = (uint32_t)(lk[p] >> 32);
+      const bool tied = (p + 1 < nk && (uint32_t)(lk[p + 1] >> 32) == h) ||
+                        (p > 0 && (uint32_t)(lk[p - 1] >> 32) == h);
+      if (tied) lz[p] = key_bits(z[(int32_t)(uint32_t)key[e]]);
     }
     __syncthreads();
     for (int e = 0; e < kZoneItems; ++e) {
