@@ -151,8 +151,11 @@ def run_mode(work, precision, schedule, steps, warmup):
                 events=st["events"] - ev0, schedule=tuned)
 
 
-def full_step(steps, warmup):
-    """Whole path on the large 2-D disk: bin -> collide -> transport per step."""
+def full_step(steps, warmup, steady=True):
+    """Whole path on the large 2-D disk: bin -> collide -> transport per step;
+    an early window (after the warm-up), a late one (steps LATE_FROM ..) and,
+    with steady, the steady state (steps STEADY_FROM ..)."""
+    import numpy as np
     import torch
     from paper_2507_21239_amd import api
     from paper_2507_21239_amd import workloads as W
@@ -199,24 +202,77 @@ def full_step(steps, warmup):
     wall_late = time.perf_counter() - t1
     gpu_late = a.elapsed_time(b) / LATE_STEPS
     late_events = sim.stats()["events"] - ev1
-    sim.close()
     n = len(work["particles"]["m"])
-    return {"workload": "2-D disk 1-100 AU: 2e6 particles, 1000 x 10 equal-count cells of 200, "
-                        "8 composition fractions, drift + settling + mixing + coagulation, "
-                        "1 yr per step, time-limited events",
-            "precision": "mixed", "schedule": "batched", "steps": steps, "warmup": warmup,
-            "particles": n, "active": int(st["n_active"]),
-            "ms_per_step": wall / steps * 1e3, "gpu_ms_per_step": gpu_main,
-            "events_per_step": events / steps, "collisions_per_s": events / wall,
-            "bin_ms": bin_ms, "tuned_schedule": tuned,
-            "late_window": {"from_step": max(LATE_FROM, done), "steps": LATE_STEPS,
-                            "ms_per_step": wall_late / LATE_STEPS * 1e3,
-                            "gpu_ms_per_step": gpu_late,
-                            "events_per_step": late_events / LATE_STEPS,
-                            "collisions_per_s": late_events / wall_late}}
+    out = {"workload": "2-D disk 1-100 AU: 2e6 particles, 1000 x 10 equal-count cells of 200, "
+                       "8 composition fractions, drift + settling + mixing + coagulation, "
+                       "1 yr per step, time-limited events",
+           "precision": "mixed", "schedule": "batched", "steps": steps, "warmup": warmup,
+           "particles": n, "active": int(st["n_active"]),
+           "ms_per_step": wall / steps * 1e3, "gpu_ms_per_step": gpu_main,
+           "events_per_step": events / steps, "collisions_per_s": events / wall,
+           "bin_ms": bin_ms, "tuned_schedule": tuned,
+           "late_window": {"from_step": max(LATE_FROM, done), "steps": LATE_STEPS,
+                           "ms_per_step": wall_late / LATE_STEPS * 1e3,
+                           "gpu_ms_per_step": gpu_late,
+                           "events_per_step": late_events / LATE_STEPS,
+                           "collisions_per_s": late_events / wall_late}}
+    if steady:
+        # the disk in its steady state (steps STEADY_FROM ..): time a window,
+        # then count one step's events per cell with the event log (the
+        # busiest cells' serial chains bound the collision launch from below)
+        at = max(LATE_FROM, done) + LATE_STEPS
+        if at < STEADY_FROM:
+            sim.step(W.YR, 0, STEADY_FROM - at)
+        ev2 = sim.stats()["events"]
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        a.record(stream)
+        sim.step(W.YR, 0, STEADY_STEPS)
+        b.record(stream)
+        torch.cuda.synchronize()
+        wall_steady = time.perf_counter() - t2
+        gpu_steady = a.elapsed_time(b) / STEADY_STEPS
+        steady_events = sim.stats()["events"] - ev2
+        # the same state under other fixed schedules (10 steps each): more or
+        # fewer workgroups per CU, and four-wave teams for the 200-particle cells
+        by_schedule = {}
+        for sm, g in ((256, 1), (256, 3), (128, 2)):
+            sim.set_schedule(sm, g)
+            sim.step(W.YR, 0, 1)
+            torch.cuda.synchronize()
+            a.record(stream)
+            sim.step(W.YR, 0, 10)
+            b.record(stream)
+            torch.cuda.synchronize()
+            by_schedule[f"{sm},{g}"] = a.elapsed_time(b) / 10
+        if tuned and "small_max" in tuned:
+            sim.set_schedule(tuned["small_max"], tuned["grid_per_cu"])
+        n_cells = len(sim.cells()["cell_start"]) - 1
+        per = 4096
+        log_buf = torch.full((n_cells * per * 4,), -2, dtype=torch.int32, device="cuda")
+        sim.set_event_log(log_buf, per)
+        sim.step(W.YR, 0, 1)
+        sim.set_event_log(None)
+        torch.cuda.synchronize()
+        per_cell = (log_buf.view(n_cells, per, 4)[:, :, 0] != -2).sum(dim=1).cpu().numpy()
+        del log_buf
+        out["steady_window"] = {
+            "from_step": max(STEADY_FROM, at), "steps": STEADY_STEPS,
+            "ms_per_step": wall_steady / STEADY_STEPS * 1e3,
+            "gpu_ms_per_step": gpu_steady,
+            "gpu_ms_per_step_by_schedule_after": by_schedule,
+            "events_per_step": steady_events / STEADY_STEPS,
+            "collisions_per_s": steady_events / wall_steady,
+            "events_per_cell_one_step": {
+                "max": int(per_cell.max()), "p99": float(np.percentile(per_cell, 99)),
+                "p90": float(np.percentile(per_cell, 90)), "median": float(np.median(per_cell)),
+                "cells_at_log_cap": int((per_cell >= per).sum())}}
+    sim.close()
+    return out
 
 
 LATE_FROM, LATE_STEPS = 20, 20
+STEADY_FROM, STEADY_STEPS = 300, 20
 CLOCK_GHZ = 2.4
 
 
@@ -224,17 +280,27 @@ def lone_cells():
     """Latency of one cell's serial event chain: a single cell alone on the
     GPU (mixed, batched schedule: one wave up to 256 particles, a four-wave
     team above), 1000 events, HIP events around the launch after one
-    warm-up step; cycles at the 2.4 GHz peak clock."""
+    warm-up step; cycles at the 2.4 GHz peak clock.  Also a 200-particle cell
+    on a four-wave team (single-wave threshold 199) and one carrying 8
+    composition fractions (the kernel variant with the composition mix)."""
     import numpy as np
     import torch
     from paper_2507_21239_amd import api
     from paper_2507_21239_amd import workloads as W
     out = {}
-    for n in (64, 200, 256, 1000):
+    for name, n, small_max, n_comp in (("64", 64, 256, 0), ("200", 200, 256, 0),
+                                       ("256", 256, 256, 0), ("1000", 1000, 256, 0),
+                                       ("200_four_wave", 200, 199, 0), ("200_comp8", 200, 256, 8)):
         work = W.c4_batched(seed=9, counts=[n], events=EVENTS_PER_CELL)
+        if n_comp:
+            work["params"] = dict(work["params"], n_comp=n_comp)
+            comp = np.zeros((n_comp, n), dtype=np.float32)
+            comp[np.arange(n) % n_comp, np.arange(n)] = 1.0
+            work["particles"]["comp"] = comp
         dev = api.to_device(work["particles"])
         sim = api.Simulation(work["params"], dev, precision="mixed", schedule="batched")
         sim.bin(api.cells_to_device(work["cells"]), max_cell=n)
+        sim.set_schedule(small_max, 0)
         sim.step(0.0, EVENTS_PER_CELL, 1)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -244,8 +310,8 @@ def lone_cells():
         torch.cuda.synchronize()
         us = a.elapsed_time(b) * 1e3 / EVENTS_PER_CELL
         sim.close()
-        out[str(n)] = {"waves": 1 if n <= 256 else 4, "us_per_event": us,
-                       "cycles_per_event": us * 1e-6 * CLOCK_GHZ * 1e9}
+        out[name] = {"particles": n, "waves": 1 if n <= small_max else 4, "n_comp": n_comp,
+                     "us_per_event": us, "cycles_per_event": us * 1e-6 * CLOCK_GHZ * 1e9}
     return out
 
 
@@ -798,7 +864,7 @@ def main():
                           "large_disk_ensemble": large_disk_ensemble(years=args.years)}), flush=True)
         return
     if args.modes == "none":
-        fs = full_step(args.steps, args.warmup)
+        fs = full_step(args.steps, args.warmup, steady=False)
         print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
                           "full_step": fs}), flush=True)
         return
@@ -849,7 +915,8 @@ def main():
         out["full_step"] = full_step(args.steps, args.warmup)
         log("full step", f"{out['full_step']['ms_per_step']:.3f} ms/step",
             f"bin {out['full_step']['bin_ms']:.3f} ms",
-            f"late {out['full_step']['late_window']['ms_per_step']:.3f} ms/step")
+            f"late {out['full_step']['late_window']['ms_per_step']:.3f} ms/step",
+            f"steady {out['full_step']['steady_window']['ms_per_step']:.3f} ms/step")
         log("lone cells")
         out["lone_cell"] = lone_cells()
     if not args.no_error:
