@@ -56,7 +56,7 @@ struct CollideArgs {
   const double *gas;        // [n_cells][6]
   const int32_t *big_list;  // cells processed by four-wave teams, largest first
   const int32_t *small_list;// cells processed by single waves, largest first
-  const Plan *plan;         // list lengths (device), grid verdict
+  const Plan *plan;         // list lengths (device), grid validation result
   int32_t big_cap, small_cap;   // particle capacity of a team's LDS region
   double *m;
   const double *M;

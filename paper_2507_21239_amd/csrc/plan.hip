@@ -18,7 +18,7 @@ __global__ void k_plan_clear(Plan *plan, uint32_t *hist, DevState *st) {
   for (int b = threadIdx.x; b < kPlanBuckets; b += blockDim.x) hist[b] = 0u;
   if (threadIdx.x == 0) {
     *plan = Plan{};
-    st->flags &= ~(uint32_t)FLAG_BAD_GRID;  // a new grid replaces the old one's verdict
+    st->flags &= ~(uint32_t)FLAG_BAD_GRID;  // a new grid replaces the old one's validation result
   }
 }
 

@@ -96,7 +96,7 @@ def test_invalid_grid_is_rejected_on_the_device_and_reported():
     with pytest.raises(api.MCDError) as e:
         sim.bin(bad)
     assert e.value.status == -1
-    # a valid grid clears the verdict
+    # a valid grid clears the bad-grid flag
     sim.bin(api.cells_to_device(work["cells"]), max_cell=1024)
     sim.step(0.0, 5, 1)
     st = sim.stats()
