@@ -335,8 +335,9 @@ def lone_cells():
 
 
 def next_rows(steps, warmup):
-    """Cost of the NEXT rows, measured on the workloads they serve (mixed, batched,
-    fixed schedule 256,0 so that no tuning trials enter the timings):
+    """Cost of the features beyond the collision step, measured on the
+    workloads they serve (mixed, batched, fixed schedule 256,0 so that no
+    tuning trials enter the timings):
     - the large disk's whole step with the power-law gas and with a gridded gas
       (48 x 24 nodes; the gas is sampled per cell, per particle in transport and
       once per cell for eta v_K);
@@ -648,7 +649,14 @@ def _gpu_disk_run(work_fn, seed, precision, steps, tune=True):
     sim.bin()
     if tune:
         choose_schedule(sim, W.YR, 0)
-    sim.step(W.YR, 0, steps)
+    done = 0
+    while done < steps:   # chunks, so that a long run reports its progress
+        k = min(2000, steps - done)
+        sim.step(W.YR, 0, k)
+        done += k
+        if done < steps:
+            torch.cuda.synchronize()
+            log("  ", precision, "seed", seed, done, "steps")
     ev = sim.stats()["events"]
     torch.cuda.synchronize()
     h = {k: dev[k].cpu().numpy() for k in ("m", "active")}
@@ -730,6 +738,108 @@ def large_disk_ensemble(seeds=16, years=1000, oracle_steps=3):
     res["mixed_vs_oracle"] = dict(compare_ensembles(orc, mix_s, "oracle", "mixed"),
                                   horizon_yr=oracle_steps, oracle_s=t2 - t1)
     return res
+
+
+LOGM_EDGES = (-16.0, 8.0, 240_000)   # log10 m histogram of a run: 1e-4 dex bins
+
+
+def _logm_hist(logm):
+    import numpy as np
+    lo, hi, nb = LOGM_EDGES
+    return np.histogram(np.clip(logm, lo, hi - 1e-9), bins=nb, range=(lo, hi))[0].astype(np.int64)
+
+
+def large_disk_ensemble_part(first, count, years, out_path, seeds=16):
+    """Runs first .. first+count-1 of the large disk's 16-seed ensembles over
+    `years` steps of 1 yr, GPU FP64 with seed s and mixed with seed 16 + s,
+    saved to out_path (per run: the summary, the event count, the wall time
+    and a histogram of log10 m of the active particles), so that a horizon
+    too long for one sitting can be run in parts and combined with
+    large_disk_ensemble_combine."""
+    import numpy as np
+    from paper_2507_21239_amd import workloads as W
+    fn = lambda seed: dict(W.c5_large_disk(seed=0), params=dict(W.c5_large_disk(seed=0)["params"], seed=seed))
+    rec = {}
+    for s in range(first, first + count):
+        for precision, seed in (("fp64", s), ("mixed", seeds + s)):
+            t0 = time.perf_counter()
+            r = _gpu_disk_run(fn, seed, precision, years)
+            wall = time.perf_counter() - t0
+            log("ensemble part:", precision, "seed", seed, f"{wall:.1f} s")
+            key = f"{precision}_{seed}"
+            rec[key + "_summary"] = np.array([r["summary"][q] for q in SUMMARY_KEYS])
+            rec[key + "_events"] = np.array(r["events"])
+            rec[key + "_wall"] = np.array(wall)
+            rec[key + "_hist"] = _logm_hist(r["logm"])
+    np.savez_compressed(out_path, years=np.array(years), **rec)
+    return {"saved": out_path, "runs": len(rec) // 4}
+
+
+SUMMARY_KEYS = ("M1/M0", "M2/M1", "M3/M2", "mass-weighted mean log10 m", "active")
+
+
+def compare_ensembles_hist(a_runs, b_runs, a_name, b_name):
+    """compare_ensembles for runs that carry a histogram of log10 m (1e-4 dex
+    bins) instead of the samples: the KS distance is the largest gap of the
+    pooled empirical distribution functions at the bin edges (exact up to
+    the mass of one bin), its p-value from the asymptotic Kolmogorov law."""
+    import numpy as np
+    from scipy import special
+    out = {"runs": {a_name: len(a_runs), b_name: len(b_runs)}, "quantities": {}}
+    ok = True
+    for k, q in enumerate(SUMMARY_KEYS):
+        xa = np.array([r["summary"][k] for r in a_runs])
+        xb = np.array([r["summary"][k] for r in b_runs])
+        sa, sb = xa.std(ddof=1) / np.sqrt(len(xa)), xb.std(ddof=1) / np.sqrt(len(xb))
+        se = float(np.hypot(sa, sb))
+        z = float((xb.mean() - xa.mean()) / se) if se > 0 else 0.0
+        ok = ok and abs(z) <= 3.0
+        out["quantities"][q] = {a_name: float(xa.mean()), a_name + "_se": float(sa),
+                                b_name: float(xb.mean()), b_name + "_se": float(sb), "z": z}
+
+    def ks(ha, hb):
+        na, nb = ha.sum(), hb.sum()
+        d = float(np.max(np.abs(np.cumsum(ha) / na - np.cumsum(hb) / nb)))
+        return d, float(special.kolmogorov(d * np.sqrt(na * nb / (na + nb)))), int(na), int(nb)
+
+    ha = sum(r["hist"] for r in a_runs)
+    hb = sum(r["hist"] for r in b_runs)
+    d, p, na, nb = ks(ha, hb)
+    half = lambda R: ks(sum(r["hist"] for r in R[: len(R) // 2]), sum(r["hist"] for r in R[len(R) // 2:]))[0]
+    ref = max(half(a_runs), half(b_runs))
+    out["logm_ks"] = {"D": d, "p": p, "D_half_vs_half": ref, "samples": [na, nb],
+                      "bins_dex": (LOGM_EDGES[1] - LOGM_EDGES[0]) / LOGM_EDGES[2]}
+    out["within_tolerance"] = bool(ok and d <= ref)
+    return out
+
+
+def large_disk_ensemble_combine(paths):
+    """Combine the parts written by large_disk_ensemble_part: mixed against
+    GPU FP64 over their common horizon."""
+    import numpy as np
+    runs = {"fp64": [], "mixed": []}
+    years = None
+    for path in paths:
+        z = np.load(path)
+        years = int(z["years"]) if years is None else years
+        if int(z["years"]) != years:
+            raise ValueError("parts of different horizons")
+        for key in z.files:
+            if key.endswith("_summary"):
+                base = key[: -len("_summary")]
+                precision = base.split("_")[0]
+                runs[precision].append({"seed": int(base.split("_")[1]), "summary": z[key],
+                                        "hist": z[base + "_hist"], "events": int(z[base + "_events"]),
+                                        "wall": float(z[base + "_wall"])})
+    for v in runs.values():
+        v.sort(key=lambda r: r["seed"])
+    out = compare_ensembles_hist(runs["fp64"], runs["mixed"], "fp64", "mixed")
+    out.update({"horizon_yr": years,
+                "fp64_seeds": [r["seed"] for r in runs["fp64"]],
+                "mixed_seeds": [r["seed"] for r in runs["mixed"]],
+                "s_per_run": {k: float(np.mean([r["wall"] for r in v])) for k, v in runs.items()},
+                "events_per_run": {k: float(np.mean([r["events"] for r in v])) for k, v in runs.items()}})
+    return out
 
 
 HOST_THREADS_MAX = 16   # the host-CPU share of one GPU on the measurement boxes
@@ -835,12 +945,20 @@ def main():
     ap.add_argument("--no-error", action="store_true", help="skip the error report")
     ap.add_argument("--modes", default="all",
                     help="all | headline | none (only the full step, for profiling) | "
-                         "next (cost of the NEXT rows) | configs (per-configuration rates, "
-                         "GPU forms and oracle) | ensemble (the large disk's 16-seed "
-                         "ensembles, mixed vs GPU FP64 and vs the oracle)")
+                         "next (cost of the sigma_d histogram, the gridded gas, the "
+                         "fragmentation criteria and the snapshots) | configs (per-configuration "
+                         "rates, GPU forms and oracle) | ensemble (the large disk's 16-seed "
+                         "ensembles, mixed vs GPU FP64 and vs the oracle) | ensemble-part (a "
+                         "part of the FP64 / mixed ensemble, saved for --combine)")
     ap.add_argument("--no-full-step", action="store_true", help="skip the full-path measurement")
     ap.add_argument("--years", type=int, default=1000,
                     help="horizon of --modes ensemble (the large disk's 16-seed ensembles)")
+    ap.add_argument("--part", default="0,16",
+                    help="--modes ensemble-part: first seed and count of this part")
+    ap.add_argument("--out", default="gpurun_out/ensemble_part.npz",
+                    help="--modes ensemble-part: where the part is saved")
+    ap.add_argument("--combine", nargs="*", default=None,
+                    help="combine saved ensemble parts (host only) and print the comparison")
     ap.add_argument("--oracle-steps", type=int, default=3,
                     help="ensemble mode: steps of the large disk's oracle comparison")
     ap.add_argument("--schedule", default=None,
@@ -850,9 +968,14 @@ def main():
                     help="only run the HBM counter calibration copy")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the collision step has no multi-GPU path in this "
-              "build (cells would shard by radial zones; see the design notes)", file=sys.stderr)
+        print("bench.py runs on one GPU: the library has no multi-GPU path (cells would shard "
+              "by contiguous ranges of radial zones)", file=sys.stderr)
         sys.exit(2)
+    if args.combine:
+        print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
+                          "large_disk_ensemble_combined": large_disk_ensemble_combine(args.combine)}),
+              flush=True)
+        return
 
     import numpy as np
     import torch
@@ -885,6 +1008,12 @@ def main():
         print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
                           "large_disk_ensemble": large_disk_ensemble(
                               years=args.years, oracle_steps=args.oracle_steps)}), flush=True)
+        return
+    if args.modes == "ensemble-part":
+        first, count = (int(x) for x in args.part.split(","))
+        print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
+                          "large_disk_ensemble_part": large_disk_ensemble_part(
+                              first, count, args.years, args.out)}), flush=True)
         return
     if args.modes == "none":
         fs = full_step(args.steps, args.warmup, steady=False)
