@@ -6,23 +6,25 @@
 // outcome (sticking / erosion / fragmentation) to i only, update every row
 // sum incrementally for the changed particle and recompute row i.
 //
-// A cell is processed by a team of nw waves (1, or 4 for cells above 256
-// particles).  The cell's n particles are in canonical order j = 0..n-1; team
-// lane t owns the contiguous slots j = t*K .. t*K+K-1 (K = ceil(n/(64 nw))),
-// so the cumulative rate of j is the team prefix of the lanes' partial sums
-// plus a short in-lane prefix.  Prefix sums are FP64 DPP scans in both
-// forms; four-wave teams exchange wave totals through LDS (one barrier per
-// scan).  A
-// selection is made by the wave whose prefix range holds the target -- every
-// wave finds it from the exchanged totals -- and published with one more
-// barrier.  The uniforms of 64 events are drawn at once, one event per lane.
-// Particle records live in LDS as packed vectors
-// indexed by s = q*64nw + t (slot q of lane t), so a wave reads consecutive
-// 16-byte words.  Row sums (FP64), the per-event row values, masses and
-// particle indices stay in registers of the owning lane; masses go back to
-// HBM once, when the cell is done.  In the FP32 form the starting row sums
-// evaluate each unordered pair once (build_rows_pairwise*); the FP64 form
-// sums every row in canonical order.
+// A cell is processed by a team of nw waves (1, or 4 for cells above the
+// single-wave threshold, 256 particles by default); the two team shapes are
+// separate instantiations of the cell body.  The cell's n particles are in
+// canonical order j = 0..n-1; team lane t owns the contiguous slots
+// j = t*K .. t*K+K-1 (K = ceil(n/(64 nw))), so the cumulative rate of j is the
+// team prefix of the lanes' partial sums plus a short in-lane prefix.  Prefix
+// sums are FP64 DPP scans in both forms; four-wave teams exchange wave totals
+// through LDS (one barrier per scan).  A selection is made by the wave whose
+// prefix range holds the target -- every wave finds it from the exchanged
+// totals -- and published with one more barrier.  The uniforms of 64 events
+// are drawn at once, one event per lane.  Particle records live in LDS as
+// packed vectors indexed by s = q*64nw + t (slot q of lane t), so a wave reads
+// consecutive 16-byte words.  Row sums (FP64), the per-event row values,
+// masses and particle indices stay in registers of the owning lane; masses go
+// back to HBM once, when the cell is done.  In the FP32 form the starting row
+// sums evaluate each unordered pair once (build_rows_pairwise*); the FP64 form
+// sums every row in canonical order.  The batched kernel carries the
+// composition mix and the event log only in the variant launched for runs
+// that use them.
 #include <algorithm>
 
 #include "device_common.hpp"
@@ -1048,8 +1050,7 @@ __global__ __launch_bounds__(256, sizeof(RT) == 4 ? 3 : 2) void collide_batched(
       process_cell<RT, KMAX, FAST, PROB, AUX, 4>(A, cell, smem, A.big_cap, wave, lane, step);
     else
       process_cell<RT, KMAX, FAST, PROB, AUX, 1>(A, cell, smem + (size_t)wave * small_bytes,
-                                                  A.small_cap,
-                                            0, lane, step);
+                                                  A.small_cap, 0, lane, step);
   }
 }
 
