@@ -1,0 +1,73 @@
+"""Host-side logic of bench.py (no GPU): the work counts behind the roofline
+figures, the ensemble comparisons behind the error report, and the refusal of
+more than one GPU."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_pair_evaluation_counts():
+    counts = np.array([1, 64, 65, 300])
+    # algorithmic: n(n+1)/2 per build plus n per event
+    assert bench.pair_evals(counts, 10) == sum(n * (n + 1) / 2 + 10 * n for n in (1, 64, 65, 300))
+    # executed, lane by lane: one wave (64 lanes) up to 256 particles, four above
+    def one(n, events):
+        if n <= 256:
+            lanes, K, offs = 64, -(-n // 64), 32
+        else:
+            lanes, K, offs = 256, -(-n // 256), 128
+        return lanes * (K * (K + 1) // 2 + offs * K * K) + events * 2 * lanes * K
+    assert bench.executed_pair_evals(counts, 10) == sum(one(n, 10) for n in (1, 64, 65, 300))
+    # the kernel never executes fewer evaluations than the method needs
+    c = np.arange(1, 1025)
+    assert bench.executed_pair_evals(c, 1000) > bench.pair_evals(c, 1000)
+
+
+def _runs(rng, n_runs, shift=0.0, n=20000):
+    runs = []
+    for _ in range(n_runs):
+        logm = rng.normal(-10.0 + shift, 1.0, n)
+        m = 10.0 ** logm
+        M = np.ones(n)
+        runs.append({"summary": bench.swarm_summary(m, M, np.ones(n, dtype=bool)), "logm": logm,
+                     "hist": bench._logm_hist(logm)})
+    return runs
+
+
+def test_ensemble_comparison_accepts_equal_and_flags_shifted_distributions():
+    rng = np.random.default_rng(1)
+    a, b = _runs(rng, 16), _runs(rng, 16)
+    assert bench.compare_ensembles(a, b, "a", "b")["within_tolerance"]
+    c = _runs(rng, 16, shift=0.05)
+    out = bench.compare_ensembles(a, c, "a", "c")
+    assert not out["within_tolerance"]
+    assert abs(out["quantities"]["mass-weighted mean log10 m"]["z"]) > 3
+
+
+def test_histogram_comparison_matches_the_sample_comparison():
+    rng = np.random.default_rng(2)
+    a, b = _runs(rng, 8), _runs(rng, 8, shift=0.01)
+    for r in a + b:
+        r["summary"] = np.array([r["summary"][q] for q in bench.SUMMARY_KEYS])
+    hist = bench.compare_ensembles_hist(a, b, "a", "b")
+    for r in a + b:
+        r["summary"] = dict(zip(bench.SUMMARY_KEYS, r["summary"]))
+    samp = bench.compare_ensembles(a, b, "a", "b")
+    # 1e-4 dex bins: the binned KS distance is the sample one within one bin's mass
+    assert abs(hist["logm_ks"]["D"] - samp["logm_ks"]["D"]) < 2e-4
+    for q in bench.SUMMARY_KEYS:
+        assert abs(hist["quantities"][q]["z"] - samp["quantities"][q]["z"]) < 1e-9
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
