@@ -71,3 +71,28 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_run_permutation_reference_accounts_for_run_to_run_spread():
+    """Runs whose whole distribution wanders from seed to seed (as the disk's
+    largest particles do): both sides draw the per-run offset from the same
+    law, so they agree, although the particle-level KS p-value says
+    otherwise; a real offset between the sides is still found."""
+    rng = np.random.default_rng(3)
+
+    def runs(n_runs, shift):
+        out = []
+        for _ in range(n_runs):
+            logm = rng.normal(-10.0 + shift + rng.normal(0.0, 0.02), 1.0, 20000)
+            out.append({"summary": bench.swarm_summary(10.0 ** logm, np.ones(len(logm)),
+                                                         np.ones(len(logm), dtype=bool)),
+                        "logm": logm})
+        return out
+
+    a, b = runs(16, 0.0), runs(16, 0.0)
+    out = bench.compare_ensembles(a, b, "a", "b")
+    assert out["logm_ks"]["p_particles"] < 0.01          # particles taken as independent
+    assert out["logm_ks"]["p_runs_permutation"] > 0.01   # runs as the sampling unit
+    assert out["within_tolerance"]
+    c = runs(16, 0.06)
+    assert bench.compare_ensembles(a, c, "a", "c")["logm_ks"]["p_runs_permutation"] < 0.01
