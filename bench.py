@@ -290,6 +290,39 @@ def full_step(steps, warmup, steady=True):
     return out
 
 
+def steady_state(steps):
+    """The large disk in its steady state alone, for profiling: STEADY_FROM
+    untimed steps (schedule tuned on the initial state, or fixed by
+    --schedule), then `steps` timed steps; in a kernel trace the last `steps`
+    launches of each kernel are the steady ones."""
+    import torch
+    from paper_2507_21239_amd import api
+    from paper_2507_21239_amd import workloads as W
+    work = W.c5_large_disk(seed=0)
+    dev = api.to_device(work["particles"])
+    sim = api.Simulation(work["params"], dev, precision="mixed", schedule="batched")
+    sim.bin()
+    tuned = choose_schedule(sim, W.YR, 0)
+    done = 0
+    while done < STEADY_FROM:
+        k = min(100, STEADY_FROM - done)
+        sim.step(W.YR, 0, k)
+        done += k
+        torch.cuda.synchronize()
+        log("steady state:", done, "steps")
+    ev0 = sim.stats()["events"]
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    sim.step(W.YR, 0, steps)
+    b.record()
+    torch.cuda.synchronize()
+    ev = sim.stats()["events"] - ev0
+    sim.close()
+    return {"from_step": STEADY_FROM, "steps": steps, "gpu_ms_per_step": a.elapsed_time(b) / steps,
+            "events_per_step": ev / steps, "tuned_schedule": tuned}
+
+
 LATE_FROM, LATE_STEPS = 20, 20
 STEADY_FROM, STEADY_STEPS = 300, 20
 CLOCK_GHZ = 2.4
@@ -985,7 +1018,8 @@ def main():
                          "fragmentation criteria and the snapshots) | configs (per-configuration "
                          "rates, GPU forms and oracle) | ensemble (the large disk's 16-seed "
                          "ensembles, mixed vs GPU FP64 and vs the oracle) | ensemble-part (a "
-                         "part of the FP64 / mixed ensemble, saved for --combine)")
+                         "part of the FP64 / mixed ensemble, saved for --combine) | steady (the "
+                         "large disk's steady state alone, for profiling)")
     ap.add_argument("--no-full-step", action="store_true", help="skip the full-path measurement")
     ap.add_argument("--years", type=int, default=1000,
                     help="horizon of --modes ensemble (the large disk's 16-seed ensembles)")
@@ -1050,6 +1084,10 @@ def main():
         print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
                           "large_disk_ensemble_part": large_disk_ensemble_part(
                               first, count, args.years, args.out)}), flush=True)
+        return
+    if args.modes == "steady":
+        print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
+                          "steady_state": steady_state(args.steps)}), flush=True)
         return
     if args.modes == "none":
         fs = full_step(args.steps, args.warmup, steady=False)
