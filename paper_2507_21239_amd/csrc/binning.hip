@@ -116,14 +116,31 @@ __device__ inline int key_shift(const BinState *bs) {
   return bits > 31 ? bits - 31 : 0;
 }
 
-__global__ __launch_bounds__(256) void k_keys_r32(const double *__restrict__ r,
-                                                 const uint8_t *__restrict__ active, int64_t N,
-                                                 const BinState *bs, uint32_t *keys, int32_t *vals) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+// 32-bit keys of one radix tile, and the tile's histogram of the first
+// digit (the first pass needs no histogram kernel of its own); elements in
+// the tile order of the radix kernels
+__global__ __launch_bounds__(256) void k_keys_r32_hist(const double *__restrict__ r,
+                                                       const uint8_t *__restrict__ active, int64_t N,
+                                                       const BinState *bs, uint32_t *keys,
+                                                       int32_t *vals, uint32_t *hist, int tiles) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0u;
+  __syncthreads();
   const int sh = key_shift(bs);
-  keys[i] = active[i] ? (uint32_t)((key_bits(r[i]) - bs->min_bits) >> sh) : 0xFFFFFFFFu;
-  vals[i] = (int32_t)i;
+  const uint64_t lo = bs->min_bits;
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+#pragma unroll
+  for (int it = 0; it < kRadixItems; ++it) {
+    const int64_t i = base + it * kRadixThreads + threadIdx.x;
+    if (i < N) {
+      const uint32_t k = active[i] ? (uint32_t)((key_bits(r[i]) - lo) >> sh) : 0xFFFFFFFFu;
+      keys[i] = k;
+      vals[i] = (int32_t)i;
+      atomicAdd(&h[k & 255u], 1u);
+    }
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
 }
 
 __global__ __launch_bounds__(256) void k_keys_from_double(const double *__restrict__ x,
@@ -282,11 +299,13 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const KeyT *__restrict__ 
   }
 }
 
+// have_hist: the tile histograms of this pass are already in hist
 template <typename KeyT>
 static hipError_t radix_pass(KeyT *const keys[2], int32_t *const vals[2], uint32_t *hist,
-                             uint32_t *digit_tot, int &cur, int64_t N, int shift, hipStream_t s) {
+                             uint32_t *digit_tot, int &cur, int64_t N, int shift, hipStream_t s,
+                             bool have_hist = false) {
   const int tiles = radix_tiles(N);
-  k_radix_hist<KeyT><<<tiles, kRadixThreads, 0, s>>>(keys[cur], N, shift, hist, tiles);
+  if (!have_hist) k_radix_hist<KeyT><<<tiles, kRadixThreads, 0, s>>>(keys[cur], N, shift, hist, tiles);
   k_radix_scan_rows<<<256, 256, 0, s>>>(hist, tiles, digit_tot);
   k_radix_scatter<KeyT><<<tiles, kRadixThreads, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1],
                                                         vals[cur ^ 1], N, shift, hist, digit_tot,
@@ -635,10 +654,13 @@ hipError_t launch_binning(const Model &P, int n_r, int n_z, const double *r, con
   const unsigned n_part = std::min<unsigned>(g1, kMinmaxParts);
   k_minmax_part<<<n_part, 256, 0, s>>>(r, active, N, b.part);
   k_minmax_final<<<1, 1024, 0, s>>>(b.part, (int)n_part, b.bs, state);
-  k_keys_r32<<<g1, 256, 0, s>>>(r, active, N, b.bs, b.k32[0], b.vals[0]);
+  const int tiles = radix_tiles(N);
+  k_keys_r32_hist<<<tiles, kRadixThreads, 0, s>>>(r, active, N, b.bs, b.k32[0], b.vals[0], b.hist,
+                                                  tiles);
   int cur = 0;
   for (int sh = 0; sh < 32; sh += 8)
-    if ((e = radix_pass<uint32_t>(b.k32, b.vals, b.hist, b.digit_tot, cur, N, sh, s)) != hipSuccess)
+    if ((e = radix_pass<uint32_t>(b.k32, b.vals, b.hist, b.digit_tot, cur, N, sh, s, sh == 0)) !=
+        hipSuccess)
       return e;
   k_ties_copy<<<g1, 256, 0, s>>>(b.k32[cur], b.vals[cur], r, N, state, b.by_r, b.flag);
   k_fix_ties<<<g1, 256, 0, s>>>(b.k32[cur], b.flag, r, N, state, b.by_r);
