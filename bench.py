@@ -328,6 +328,49 @@ STEADY_FROM, STEADY_STEPS = 300, 20
 CLOCK_GHZ = 2.4
 
 
+def _lone_sim(n, small_max, n_comp, events, grid_per_cu):
+    """A Simulation holding one cell of n particles (the batched workload's
+    particle recipe), n_comp one-hot composition fractions, mixed, batched."""
+    import numpy as np
+    from paper_2507_21239_amd import api
+    from paper_2507_21239_amd import workloads as W
+    work = W.c4_batched(seed=9, counts=[n], events=events)
+    if n_comp:
+        work["params"] = dict(work["params"], n_comp=n_comp)
+        comp = np.zeros((n_comp, n), dtype=np.float32)
+        comp[np.arange(n) % n_comp, np.arange(n)] = 1.0
+        work["particles"]["comp"] = comp
+    dev = api.to_device(work["particles"])
+    sim = api.Simulation(work["params"], dev, precision="mixed", schedule="batched")
+    sim.bin(api.cells_to_device(work["cells"]), max_cell=n)
+    sim.set_schedule(small_max, grid_per_cu)
+    return sim
+
+
+def lone_counting(spec, events, launches):
+    """One cell alone for instruction counters: spec "N" or "N,n_comp" (one
+    wave up to 256 particles, a four-wave team above), `launches` collision
+    launches of `events` events each after one warm-up launch, one workgroup
+    per CU (fewer idle waves in the counters).  Two runs that differ only in
+    `events` give the counts per event as the difference."""
+    import torch
+    parts = [int(x) for x in spec.split(",")]
+    n, n_comp = parts[0], (parts[1] if len(parts) > 1 else 0)
+    sim = _lone_sim(n, 256, n_comp, events, 1)
+    sim.step(0.0, events, 1)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    sim.step(0.0, events, launches)
+    b.record()
+    torch.cuda.synchronize()
+    out = {"particles": n, "n_comp": n_comp, "events_per_launch": events, "launches": launches,
+           "us_per_launch": a.elapsed_time(b) * 1e3 / launches,
+           "events_total": int(sim.stats()["events"])}
+    sim.close()
+    return out
+
+
 def lone_cells():
     """Latency of one cell's serial event chain: a single cell alone on the
     GPU (mixed, batched schedule: one wave up to 256 particles, a four-wave
@@ -335,24 +378,12 @@ def lone_cells():
     warm-up step; cycles at the 2.4 GHz peak clock.  Also a 200-particle cell
     on a four-wave team (single-wave threshold 199) and one carrying 8
     composition fractions (the kernel variant with the composition mix)."""
-    import numpy as np
     import torch
-    from paper_2507_21239_amd import api
-    from paper_2507_21239_amd import workloads as W
     out = {}
     for name, n, small_max, n_comp in (("64", 64, 256, 0), ("200", 200, 256, 0),
                                        ("256", 256, 256, 0), ("1000", 1000, 256, 0),
                                        ("200_four_wave", 200, 199, 0), ("200_comp8", 200, 256, 8)):
-        work = W.c4_batched(seed=9, counts=[n], events=EVENTS_PER_CELL)
-        if n_comp:
-            work["params"] = dict(work["params"], n_comp=n_comp)
-            comp = np.zeros((n_comp, n), dtype=np.float32)
-            comp[np.arange(n) % n_comp, np.arange(n)] = 1.0
-            work["particles"]["comp"] = comp
-        dev = api.to_device(work["particles"])
-        sim = api.Simulation(work["params"], dev, precision="mixed", schedule="batched")
-        sim.bin(api.cells_to_device(work["cells"]), max_cell=n)
-        sim.set_schedule(small_max, 0)
+        sim = _lone_sim(n, small_max, n_comp, EVENTS_PER_CELL, 0)
         sim.step(0.0, EVENTS_PER_CELL, 1)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -1019,7 +1050,8 @@ def main():
                          "rates, GPU forms and oracle) | ensemble (the large disk's 16-seed "
                          "ensembles, mixed vs GPU FP64 and vs the oracle) | ensemble-part (a "
                          "part of the FP64 / mixed ensemble, saved for --combine) | steady (the "
-                         "large disk's steady state alone, for profiling)")
+                         "large disk's steady state alone, for profiling) | lone (one cell "
+                         "alone, --lone and --events, --steps launches, for instruction counters)")
     ap.add_argument("--no-full-step", action="store_true", help="skip the full-path measurement")
     ap.add_argument("--years", type=int, default=1000,
                     help="horizon of --modes ensemble (the large disk's 16-seed ensembles)")
@@ -1034,6 +1066,10 @@ def main():
     ap.add_argument("--schedule", default=None,
                     help="SMALL_MAX,GRID_PER_CU: fixed batched schedule instead of the autotuner "
                          "(profiling runs, so that no tuning trials enter the kernel statistics)")
+    ap.add_argument("--lone", default="200",
+                    help="--modes lone: the cell, N or N,n_comp")
+    ap.add_argument("--events", type=int, default=EVENTS_PER_CELL,
+                    help="--modes lone: events per collision launch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the HBM counter calibration copy")
     args = ap.parse_args()
@@ -1084,6 +1120,11 @@ def main():
         print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
                           "large_disk_ensemble_part": large_disk_ensemble_part(
                               first, count, args.years, args.out)}), flush=True)
+        return
+    if args.modes == "lone":
+        print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
+                          "lone_cell": lone_counting(args.lone, args.events, args.steps)}),
+              flush=True)
         return
     if args.modes == "steady":
         print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
