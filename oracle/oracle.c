@@ -16,10 +16,15 @@
  * Pins (tests/): Philox known-answer vectors; the constant- and linear-kernel
  * Smoluchowski solutions; swarm-mass conservation; closed forms of every
  * relative-velocity source; the midplane Epstein identity; drag-law
- * continuity; selection frequencies against brute-force probabilities;
- * waiting-time and fragment-mass distributions; binning against a library
- * sort; the settling-mixing equilibrium.  Parity unpinned: the physical
- * configurations against mcdust itself (no code or output data exists).
+ * continuity; whole rate matrices of small cells at 50 digits from the
+ * physical definitions in other arrangements; selection frequencies against
+ * brute-force probabilities; waiting-time and fragment-mass distributions;
+ * the null events left by rounding residue; composition mixing in
+ * hand-worked collisions and in whole monomers; binning against a library
+ * sort; the settling-mixing equilibrium; the planar diffusion law of the
+ * radial walk and radially well-mixed tracers.  Parity unpinned: the
+ * physical configurations against mcdust itself (no code or output data
+ * exists).
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp (no fast-math).  Summation is
  * plain left-to-right; no blocking or reordering.
