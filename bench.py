@@ -53,15 +53,17 @@ EVENTS_PER_CELL = 1000
 # of WRITE_SIZE: factors 2.0 and 1.0).
 # Valid only for the kernel sources it was taken on: their SHA-256 is kept
 # and compared at run time; on any change `traffic` is reported as null.
-TRAFFIC = {"fetch_kib": 17844.0, "write_kib": 22789.81, "fetch_factor": 1.99994, "write_factor": 1.0,
-           "sources_sha256": "0003a7320ab8f9a17497bb88faf110b02bae62dcb182f36a26b2e5ce7d458a59"}
+TRAFFIC = {"fetch_kib": 19100.88, "write_kib": 22273.81, "fetch_factor": 1.99994, "write_factor": 1.0,
+           "sources_sha256": "26cb6cf61a8c76e47806c1dcb33b9eab5ecf559f4db34bc755e4f97ccf8dd63b"}
 # Issue rate of the same launch from one `rocprofv3 --pmc` pass of SQ counters:
 # VALU busy = 4 * SQ_ACTIVE_INST_VALU / (1024 SIMDs * launch cycles at 2.4 GHz),
 # and SQ_INSTS_VALU per collision; the same validity rule as TRAFFIC.
-ISSUE = {"valu_busy": 0.842, "valu_insts_per_collision": 1637,
-         "sources_sha256": "0003a7320ab8f9a17497bb88faf110b02bae62dcb182f36a26b2e5ce7d458a59"}
-KERNEL_SOURCES = ("paper_2507_21239_amd/csrc/collide.hip", "paper_2507_21239_amd/csrc/physics.hpp",
-                  "paper_2507_21239_amd/csrc/device_common.hpp", "paper_2507_21239_amd/csrc/internal.hpp")
+ISSUE = {"valu_busy": 0.844, "valu_insts_per_collision": 1631,
+         "sources_sha256": "26cb6cf61a8c76e47806c1dcb33b9eab5ecf559f4db34bc755e4f97ccf8dd63b"}
+KERNEL_SOURCES = ("paper_2507_21239_amd/csrc/collide.hip", "paper_2507_21239_amd/csrc/collide_device.hpp",
+                  "paper_2507_21239_amd/csrc/collide_ilp.hip", "paper_2507_21239_amd/csrc/physics.hpp",
+                  "paper_2507_21239_amd/csrc/device_common.hpp", "paper_2507_21239_amd/csrc/internal.hpp",
+                  "paper_2507_21239_amd/build.py")
 
 
 def kernel_sources_sha256():

@@ -3,7 +3,8 @@
 hipcc cross-compiles without a GPU.  Flags: -O3, no FP contraction (the FP64
 path keeps the operation order of its formulas; FP32 code asks for fused
 multiply-adds explicitly where it wants them), packed FP32 instructions
-disabled.
+disabled.  collide_ilp.hip (the batched kernel of the mixed form without the
+composition mix) is also scheduled for instruction-level parallelism.
 """
 from __future__ import annotations
 
@@ -17,8 +18,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmcd.so")
-SOURCES = ["capi.hip", "collide.hip", "binning.hip", "plan.hip", "transport.hip", "diagnostics.hip",
-           "noalloc.hip"]
+SOURCES = ["capi.hip", "collide.hip", "collide_ilp.hip", "binning.hip", "plan.hip", "transport.hip",
+           "diagnostics.hip", "noalloc.hip"]
+# per-file flags on top of CFLAGS
+EXTRA = {"collide_ilp.hip": ["-mllvm", "--amdgpu-sched-strategy=max-ilp"]}
 ARCH = os.environ.get("MCD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -32,7 +35,7 @@ CFLAGS = [
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *CFLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
