@@ -6,8 +6,10 @@
 // event log (the form of runs that track neither) is instantiated in
 // collide_ilp.hip, compiled with the scheduling strategy that maximises
 // instruction-level parallelism: its four-wave teams and lone cells wait
-// less on dependencies.  The variant with the composition mix keeps the
-// default schedule, under which it spills less.
+// less on dependencies.  It comes in two instantiations, one for either
+// event budget and one for fixed event counts only (no waiting times).  The
+// variant with the composition mix keeps the default schedule, under which
+// it spills less.
 #include <algorithm>
 
 #include "collide_device.hpp"
@@ -16,6 +18,8 @@ namespace mcd {
 
 // defined in collide_ilp.hip
 extern template __global__ void collide_batched<float, 4, true, false, false>(CollideArgs A);
+extern template __global__ void collide_batched<float, 4, true, false, false, kFixedCount>(
+    CollideArgs A);
 
 __global__ void reset_queues(DevState *st) {
   st->big_head = 0;
@@ -78,6 +82,10 @@ static hipError_t run_batched(const CollideArgs &a, int grid_override, hipStream
   const bool aux = (a.comp != nullptr && a.P.n_comp > 0) || a.evlog != nullptr;
   auto kern = aux ? collide_batched<RT, KMAX, FAST, PROB, true>
                   : collide_batched<RT, KMAX, FAST, PROB, false>;
+  // the mixed form's kernel without them also comes without waiting times,
+  // for fixed event counts
+  if constexpr (sizeof(RT) == 4 && KMAX == 4 && FAST && !PROB)
+    if (!aux && !(a.dt > 0.0)) kern = collide_batched<RT, KMAX, FAST, PROB, false, kFixedCount>;
   hipError_t e = prepare(kern, lds);
   int dev = 0, cus = 0, per_cu = 0;
   if (e == hipSuccess) e = hipGetDevice(&dev);

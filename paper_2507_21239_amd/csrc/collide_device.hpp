@@ -608,10 +608,15 @@ __device__ inline void log_event(const CollideArgs &A, int cell, uint32_t e, int
   }
 }
 
+// the event budget a kernel is compiled for: a fixed number of events per
+// cell (dt = 0), a time limit dt > 0, or either, read from the arguments
+enum : int { kFixedCount = 0, kTimeLimited = 1, kEitherLimit = 2 };
+
 // AUX: the composition mix and the event log are compiled in (a launch with
 // fractions to track or events to record); without them the event loop
-// carries neither
-template <typename RT, int KMAX, bool FAST, bool PROB, bool AUX, int NW>
+// carries neither.  LIMIT: a kernel compiled for fixed counts only carries no
+// waiting times (their logarithm, the time test, the priority rule)
+template <typename RT, int KMAX, bool FAST, bool PROB, bool AUX, int NW, int LIMIT = kEitherLimit>
 __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap, int wave,
                              int lane, uint32_t step) {
   constexpr int nw = NW;  // waves of the team: 1, or 4 (a compile-time shape per cell body)
@@ -758,7 +763,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
   uint32_t e = 0;  // events so far (fewer than 2^32 per cell and step)
   uint32_t oc_count[4] = {0u, 0u, 0u, 0u};
   const uint32_t c32 = (uint32_t)cell;
-  const bool timed = A.dt > 0.0;
+  const bool timed = LIMIT == kEitherLimit ? A.dt > 0.0 : LIMIT == kTimeLimited;
   const uint32_t emax = A.max_events > 0 ? (uint32_t)A.max_events : 0xFFFFFFFFu;
   double part = 0.0, Rtot;
 #pragma unroll
@@ -1022,7 +1027,7 @@ __device__ void process_cell(const CollideArgs &A, int cell, char *base, int cap
 // on four-wave teams (largest first), then small cells on single waves
 // (largest first), each wave popping its own work
 // ---------------------------------------------------------------------------
-template <typename RT, int KMAX, bool FAST, bool PROB, bool AUX>
+template <typename RT, int KMAX, bool FAST, bool PROB, bool AUX, int LIMIT = kEitherLimit>
 __global__ __launch_bounds__(256, sizeof(RT) == 4 ? 3 : 2) void collide_batched(CollideArgs A) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_item;
@@ -1053,9 +1058,9 @@ __global__ __launch_bounds__(256, sizeof(RT) == 4 ? 3 : 2) void collide_batched(
       cell = __builtin_amdgcn_readfirstlane(A.small_list[item]);
     }
     if (nw == 4)
-      process_cell<RT, KMAX, FAST, PROB, AUX, 4>(A, cell, smem, A.big_cap, wave, lane, step);
+      process_cell<RT, KMAX, FAST, PROB, AUX, 4, LIMIT>(A, cell, smem, A.big_cap, wave, lane, step);
     else
-      process_cell<RT, KMAX, FAST, PROB, AUX, 1>(A, cell, smem + (size_t)wave * small_bytes,
+      process_cell<RT, KMAX, FAST, PROB, AUX, 1, LIMIT>(A, cell, smem + (size_t)wave * small_bytes,
                                                   A.small_cap, 0, lane, step);
   }
 }
