@@ -3,7 +3,11 @@ mix and the event log compiled in (a launch with fractions to track or an
 event log set) and without them.  Apart from those two side effects they
 evaluate the same arithmetic in the same order, so on the same inputs they
 must take the same events: final masses bit-identical, in both precisions,
-with a fixed event count and with time-limited steps."""
+with a fixed event count and with time-limited steps.  In the mixed form
+the variant without them is also instantiated for fixed event counts only
+(no waiting times) and built with another instruction schedule; the
+fixed-count case compares that instantiation with the variant compiled for
+either event budget."""
 import numpy as np
 import pytest
 
