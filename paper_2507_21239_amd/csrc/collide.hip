@@ -7,9 +7,10 @@
 // collide_ilp.hip, compiled with the scheduling strategy that maximises
 // instruction-level parallelism: its four-wave teams and lone cells wait
 // less on dependencies.  It comes in two instantiations, one for either
-// event budget and one for fixed event counts only (no waiting times).  The
-// variant with the composition mix keeps the default schedule, under which
-// it spills less.
+// event budget and one for fixed event counts only (no waiting times); the
+// FP64 form's kernel without them is instantiated there for fixed counts
+// too.  The variant with the composition mix keeps the default schedule,
+// under which it spills less.
 #include <algorithm>
 
 #include "collide_device.hpp"
@@ -19,6 +20,8 @@ namespace mcd {
 // defined in collide_ilp.hip
 extern template __global__ void collide_batched<float, 4, true, false, false>(CollideArgs A);
 extern template __global__ void collide_batched<float, 4, true, false, false, kFixedCount>(
+    CollideArgs A);
+extern template __global__ void collide_batched<double, 4, false, false, false, kFixedCount>(
     CollideArgs A);
 
 __global__ void reset_queues(DevState *st) {
@@ -82,9 +85,10 @@ static hipError_t run_batched(const CollideArgs &a, int grid_override, hipStream
   const bool aux = (a.comp != nullptr && a.P.n_comp > 0) || a.evlog != nullptr;
   auto kern = aux ? collide_batched<RT, KMAX, FAST, PROB, true>
                   : collide_batched<RT, KMAX, FAST, PROB, false>;
-  // the mixed form's kernel without them also comes without waiting times,
-  // for fixed event counts
-  if constexpr (sizeof(RT) == 4 && KMAX == 4 && FAST && !PROB)
+  // the kernels without them of the mixed form's fast path and of the FP64
+  // form (up to 4 slots per lane) also come without waiting times, for fixed
+  // event counts
+  if constexpr (KMAX == 4 && !PROB && (sizeof(RT) == 8 || FAST))
     if (!aux && !(a.dt > 0.0)) kern = collide_batched<RT, KMAX, FAST, PROB, false, kFixedCount>;
   hipError_t e = prepare(kern, lds);
   int dev = 0, cus = 0, per_cu = 0;
