@@ -849,24 +849,27 @@ def _ks_permutation_p(hists_a, hists_b, n_perm=1000):
     return float((np.sum(dist(sel) >= d0) + 1) / (n_perm + 1))
 
 
-def large_disk_ensemble_part(first, count, years, out_path, seeds=16):
+def large_disk_ensemble_part(first, count, years, out_path, seeds=16, sides=("fp64", "mixed")):
     """Runs first .. first+count-1 of the large disk's 16-seed ensembles over
-    `years` steps of 1 yr, GPU FP64 with seed s and mixed with seed 16 + s,
-    saved to out_path (per run: the summary, the event count, the wall time
-    and a histogram of log10 m of the active particles), so that a horizon
-    too long for one sitting can be run in parts and combined with
-    large_disk_ensemble_combine."""
+    `years` steps of 1 yr, for each of `sides`: GPU FP64 with seed s, the
+    oracle with seed s (on the host CPU only), mixed with seed 16 + s; saved to
+    out_path (per run: the summary, the event count, the wall time and a
+    histogram of log10 m of the active particles), so that a horizon too long
+    for one sitting can be run in parts, and the oracle apart from the GPU,
+    and combined with large_disk_ensemble_combine."""
     import numpy as np
     from paper_2507_21239_amd import workloads as W
     fn = lambda seed: dict(W.c5_large_disk(seed=0), params=dict(W.c5_large_disk(seed=0)["params"], seed=seed))
     rec = {}
     for s in range(first, first + count):
-        for precision, seed in (("fp64", s), ("mixed", seeds + s)):
+        for side in sides:
+            seed = seeds + s if side == "mixed" else s
             t0 = time.perf_counter()
-            r = _gpu_disk_run(fn, seed, precision, years)
+            r = _oracle_disk_run(fn, seed, years) if side == "oracle" else \
+                _gpu_disk_run(fn, seed, side, years)
             wall = time.perf_counter() - t0
-            log("ensemble part:", precision, "seed", seed, f"{wall:.1f} s")
-            key = f"{precision}_{seed}"
+            log("ensemble part:", side, "seed", seed, f"{wall:.1f} s")
+            key = f"{side}_{seed}"
             rec[key + "_summary"] = np.array([r["summary"][q] for q in SUMMARY_KEYS])
             rec[key + "_events"] = np.array(r["events"])
             rec[key + "_wall"] = np.array(wall)
@@ -917,9 +920,9 @@ def compare_ensembles_hist(a_runs, b_runs, a_name, b_name):
 
 def large_disk_ensemble_combine(paths):
     """Combine the parts written by large_disk_ensemble_part: mixed against
-    GPU FP64 over their common horizon."""
+    GPU FP64, or against the oracle, over their common horizon."""
     import numpy as np
-    runs = {"fp64": [], "mixed": []}
+    runs = {"fp64": [], "oracle": [], "mixed": []}
     years = None
     for path in paths:
         z = np.load(path)
@@ -929,15 +932,19 @@ def large_disk_ensemble_combine(paths):
         for key in z.files:
             if key.endswith("_summary"):
                 base = key[: -len("_summary")]
-                precision = base.split("_")[0]
-                runs[precision].append({"seed": int(base.split("_")[1]), "summary": z[key],
-                                        "hist": z[base + "_hist"], "events": int(z[base + "_events"]),
-                                        "wall": float(z[base + "_wall"])})
+                side = base.split("_")[0]
+                runs[side].append({"seed": int(base.split("_")[1]), "summary": z[key],
+                                   "hist": z[base + "_hist"], "events": int(z[base + "_events"]),
+                                   "wall": float(z[base + "_wall"])})
     for v in runs.values():
         v.sort(key=lambda r: r["seed"])
-    out = compare_ensembles_hist(runs["fp64"], runs["mixed"], "fp64", "mixed")
+    runs = {k: v for k, v in runs.items() if v}
+    ref = "fp64" if "fp64" in runs else "oracle"
+    if ref not in runs or "mixed" not in runs:
+        raise ValueError("the parts hold no mixed runs, or no FP64 or oracle runs to compare them with")
+    out = compare_ensembles_hist(runs[ref], runs["mixed"], ref, "mixed")
     out.update({"horizon_yr": years,
-                "fp64_seeds": [r["seed"] for r in runs["fp64"]],
+                f"{ref}_seeds": [r["seed"] for r in runs[ref]],
                 "mixed_seeds": [r["seed"] for r in runs["mixed"]],
                 "s_per_run": {k: float(np.mean([r["wall"] for r in v])) for k, v in runs.items()},
                 "events_per_run": {k: float(np.mean([r["events"] for r in v])) for k, v in runs.items()}})
@@ -1061,6 +1068,9 @@ def main():
                     help="--modes ensemble-part: first seed and count of this part")
     ap.add_argument("--out", default="gpurun_out/ensemble_part.npz",
                     help="--modes ensemble-part: where the part is saved")
+    ap.add_argument("--sides", default="fp64,mixed",
+                    help="--modes ensemble-part: which of fp64, oracle, mixed to run (oracle "
+                         "alone needs no GPU)")
     ap.add_argument("--combine", nargs="*", default=None,
                     help="combine saved ensemble parts (host only) and print the comparison")
     ap.add_argument("--oracle-steps", type=int, default=3,
@@ -1083,6 +1093,16 @@ def main():
         print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
                           "large_disk_ensemble_combined": large_disk_ensemble_combine(args.combine)}),
               flush=True)
+        return
+    sides = tuple(x for x in args.sides.split(",") if x)
+    if not sides or set(sides) - {"fp64", "oracle", "mixed"}:
+        print("--sides takes fp64, oracle and mixed", file=sys.stderr)
+        sys.exit(2)
+    if args.modes == "ensemble-part" and sides == ("oracle",):
+        first, count = (int(x) for x in args.part.split(","))
+        print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
+                          "large_disk_ensemble_part": large_disk_ensemble_part(
+                              first, count, args.years, args.out, sides=sides)}), flush=True)
         return
 
     import numpy as np
@@ -1121,7 +1141,7 @@ def main():
         first, count = (int(x) for x in args.part.split(","))
         print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
                           "large_disk_ensemble_part": large_disk_ensemble_part(
-                              first, count, args.years, args.out)}), flush=True)
+                              first, count, args.years, args.out, sides=sides)}), flush=True)
         return
     if args.modes == "lone":
         print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",

@@ -6,6 +6,7 @@ import subprocess
 import sys
 
 import numpy as np
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -96,3 +97,33 @@ def test_run_permutation_reference_accounts_for_run_to_run_spread():
     assert out["within_tolerance"]
     c = runs(16, 0.06)
     assert bench.compare_ensembles(a, c, "a", "c")["logm_ks"]["p_runs_permutation"] < 0.01
+
+
+def test_parts_combine_against_the_oracle(tmp_path):
+    """Ensemble parts saved apart (the oracle's runs on the host, the mixed
+    runs from the GPU) combine into one comparison against the oracle; a part
+    set without a reference side is refused, and so is an unknown side."""
+    rng = np.random.default_rng(4)
+
+    def save(path, side, seeds, shift):
+        rec = {}
+        for s in seeds:
+            logm = rng.normal(-10.0 + shift, 1.0, 20000)
+            summ = bench.swarm_summary(10.0 ** logm, np.ones(len(logm)), np.ones(len(logm), dtype=bool))
+            key = f"{side}_{s}"
+            rec[key + "_summary"] = np.array([summ[q] for q in bench.SUMMARY_KEYS])
+            rec[key + "_events"] = np.array(100)
+            rec[key + "_wall"] = np.array(1.0)
+            rec[key + "_hist"] = bench._logm_hist(logm)
+        np.savez_compressed(path, years=np.array(5), **rec)
+
+    save(tmp_path / "o.npz", "oracle", range(8), 0.0)
+    save(tmp_path / "m.npz", "mixed", range(8, 16), 0.0)
+    out = bench.large_disk_ensemble_combine([str(tmp_path / "o.npz"), str(tmp_path / "m.npz")])
+    assert out["oracle_seeds"] == list(range(8)) and out["mixed_seeds"] == list(range(8, 16))
+    assert out["within_tolerance"] and out["horizon_yr"] == 5
+    with pytest.raises(ValueError):
+        bench.large_disk_ensemble_combine([str(tmp_path / "m.npz")])
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--modes", "ensemble-part",
+                        "--sides", "oracle,gpu"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "--sides" in r.stderr
