@@ -849,21 +849,23 @@ def _ks_permutation_p(hists_a, hists_b, n_perm=1000):
     return float((np.sum(dist(sel) >= d0) + 1) / (n_perm + 1))
 
 
-def large_disk_ensemble_part(first, count, years, out_path, seeds=16, sides=("fp64", "mixed")):
+def large_disk_ensemble_part(first, count, years, out_path, seeds=16, sides=("fp64", "mixed"),
+                             same_seeds=False):
     """Runs first .. first+count-1 of the large disk's 16-seed ensembles over
     `years` steps of 1 yr, for each of `sides`: GPU FP64 with seed s, the
     oracle with seed s (on the host CPU only), mixed with seed 16 + s; saved to
     out_path (per run: the summary, the event count, the wall time and a
     histogram of log10 m of the active particles), so that a horizon too long
     for one sitting can be run in parts, and the oracle apart from the GPU,
-    and combined with large_disk_ensemble_combine."""
+    and combined with large_disk_ensemble_combine.  same_seeds: the mixed runs
+    take seed s too (shared Philox streams, for a paired comparison)."""
     import numpy as np
     from paper_2507_21239_amd import workloads as W
     fn = lambda seed: dict(W.c5_large_disk(seed=0), params=dict(W.c5_large_disk(seed=0)["params"], seed=seed))
     rec = {}
     for s in range(first, first + count):
         for side in sides:
-            seed = seeds + s if side == "mixed" else s
+            seed = seeds + s if side == "mixed" and not same_seeds else s
             t0 = time.perf_counter()
             r = _oracle_disk_run(fn, seed, years) if side == "oracle" else \
                 _gpu_disk_run(fn, seed, side, years)
@@ -948,6 +950,13 @@ def large_disk_ensemble_combine(paths):
                 "mixed_seeds": [r["seed"] for r in runs["mixed"]],
                 "s_per_run": {k: float(np.mean([r["wall"] for r in v])) for k, v in runs.items()},
                 "events_per_run": {k: float(np.mean([r["events"] for r in v])) for k, v in runs.items()}})
+    seeds_ref = [r["seed"] for r in runs[ref]]
+    if seeds_ref == [r["seed"] for r in runs["mixed"]] and len(seeds_ref) > 1:
+        # the same seeds on both sides: collisions per run compared run by run
+        d = np.array([m["events"] / a["events"] - 1.0 for a, m in zip(runs[ref], runs["mixed"])])
+        se = float(d.std(ddof=1) / np.sqrt(len(d)))
+        out["paired_collisions"] = {"rel_diff_mean": float(d.mean()), "rel_diff_se": se,
+                                    "z": float(d.mean() / se) if se > 0 else 0.0}
     return out
 
 
@@ -1071,6 +1080,8 @@ def main():
     ap.add_argument("--sides", default="fp64,mixed",
                     help="--modes ensemble-part: which of fp64, oracle, mixed to run (oracle "
                          "alone needs no GPU)")
+    ap.add_argument("--same-seeds", action="store_true",
+                    help="--modes ensemble-part: the mixed runs take the other sides' seeds")
     ap.add_argument("--combine", nargs="*", default=None,
                     help="combine saved ensemble parts (host only) and print the comparison")
     ap.add_argument("--oracle-steps", type=int, default=3,
@@ -1141,7 +1152,8 @@ def main():
         first, count = (int(x) for x in args.part.split(","))
         print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",
                           "large_disk_ensemble_part": large_disk_ensemble_part(
-                              first, count, args.years, args.out, sides=sides)}), flush=True)
+                              first, count, args.years, args.out, sides=sides,
+                              same_seeds=args.same_seeds)}), flush=True)
         return
     if args.modes == "lone":
         print(json.dumps({"metric": METRIC, "value": None, "unit": "collisions/s",

@@ -122,8 +122,13 @@ def test_parts_combine_against_the_oracle(tmp_path):
     out = bench.large_disk_ensemble_combine([str(tmp_path / "o.npz"), str(tmp_path / "m.npz")])
     assert out["oracle_seeds"] == list(range(8)) and out["mixed_seeds"] == list(range(8, 16))
     assert out["within_tolerance"] and out["horizon_yr"] == 5
+    assert "paired_collisions" not in out
     with pytest.raises(ValueError):
         bench.large_disk_ensemble_combine([str(tmp_path / "m.npz")])
+    # the same seeds on both sides: collisions per run compared run by run
+    save(tmp_path / "p.npz", "mixed", range(8), 0.0)
+    out = bench.large_disk_ensemble_combine([str(tmp_path / "o.npz"), str(tmp_path / "p.npz")])
+    assert out["paired_collisions"]["rel_diff_mean"] == 0.0
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--modes", "ensemble-part",
                         "--sides", "oracle,gpu"], capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "--sides" in r.stderr
